@@ -1,0 +1,163 @@
+"""Throughput of the training step on one MI355X.
+
+A step is one pass of the whole hot path over one batch: rays of one view -> samples -> hash encode
+-> LayerNorm -> MLP -> ray sums (Eq. 1) -> L1 loss (Eq. 3) -> backward with table scatter-add ->
+Adam on every parameter.  Workload: the 256^3 synthetic phantom (20 random ellipsoids), 50 cone-beam
+views on a 256 x 256 detector with Poisson noise at I0 = 1e5, 16 levels x 2 features, T = 2^19,
+base resolution 16 (max 2048), MLP 4 x 32, 192 samples per ray, 2048 rays per step, FP32.
+Projections are resident in HBM before the timed region; every draw (view order, pixels, jitter)
+happens on the device.
+
+Prints one JSON line: value = sample points per second of full steps (rays * samples * steps /
+seconds), roofline of the dominant kernel from HIP events on the library's stream, and the FP64
+oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "train pts/s (fwd+bwd); secs to 30 dB PSNR, BF16+MCI vs plain FP32"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(cfg, lay, n_points):
+    """Bytes each kernel must move by definition (per launch), for the roofline.
+
+    forward:  per point the 8-corner gathers of every level (L * 8 * F * 4 B) + the stored encoding
+              (C * 4 B);
+    backward: per point the reloaded encoding (C * 4 B) + the scatter-add payload of every corner
+              (L * 8 * F * 4 B);
+    adam:     per parameter read p, g, m, v and write p, m, v, g (32 B).
+    """
+    L, F = cfg.n_levels, cfg.feats_per_level
+    C = L * F
+    gather = L * 8 * F * 4
+    return {
+        "forward": n_points * (gather + C * 4),
+        "backward": n_points * (C * 4 + gather),
+        "adam": lay["n_params_padded"] * 32,
+        "per_point": {"forward": gather + C * 4, "backward": C * 4 + gather},
+    }
+
+
+def cpu_baseline(w, g, A, n_rays_sample=384):
+    """FP64 oracle (single thread) on a bounded sample: n_rays_sample rays of one view forward +
+    backward, plus one dense Adam over all parameters; scaled to the full step of R rays."""
+    import oracle as ora
+    ora.build(force=False)
+    from paper_2506_19742_amd import synth
+    oc = ora.Config(w.n_levels, w.feats, w.log2_table, w.base_res, w.max_res, w.depth, w.width)
+    tot, nt, nd = ora.n_params(oc)
+    p = ora.init_params(oc, 1)
+    pix, jit = synth.ray_batch(3, g.n_pix, n_rays_sample, w.samples)
+    t0 = time.perf_counter()
+    _, _, grad = ora.ray_batch(oc, g, p, float(g.angles[0]), A[0], pix, jit)
+    t_rays = time.perf_counter() - t0
+    m, v = np.zeros(tot), np.zeros(tot)
+    t0 = time.perf_counter()
+    ora.adam(p, grad, m, v, 1)
+    t_adam = time.perf_counter() - t0
+    step_s = t_rays * (w.rays / n_rays_sample) + t_adam
+    return {"value": w.rays * w.samples / step_s, "unit": "pts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_rays_sample} rays x {w.samples} samples fwd+bwd ({t_rays:.1f} s) + one "
+                      f"Adam over {tot} params ({t_adam:.2f} s), scaled to {w.rays} rays/step",
+            "fwd_bwd_pts_per_s": n_rays_sample * w.samples / t_rays}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="ct256")
+    ap.add_argument("--precision", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build measures "
+              "the single-GPU training step; multi-GPU sharding is design-only.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_19742_amd import nic, synth
+
+    w = synth.WORKLOADS[args.workload]
+    over = {} if args.precision is None else {"precision": args.precision}
+    cfg = nic.config_for(w, seed=2024, **over)
+    print(f"[bench] workload {w.name}: generating scan", file=sys.stderr, flush=True)
+    ph, g, A = synth.scan(w)
+    dev = torch.device("cuda:0")
+    proj = torch.tensor(A, device=dev)
+    model = nic.Model(cfg, g)
+    model.set_projections(proj)
+    lay = model.layout
+    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    model.train(args.warmup, want_loss=False)
+    torch.cuda.synchronize()
+
+    model.set_timing(True)
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model.train(args.steps, want_loss=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = model.kernel_times()
+    model.set_timing(False)
+    losses = model.train(1)
+
+    P = w.rays * w.samples
+    value = P * args.steps / dt
+    ab = algorithmic_bytes(cfg, lay, P)
+    per_kernel = {k: {"avg_ms": (ms / n if n else None), "launches": n} for k, (ms, n) in kt.items()}
+    dom = max(("forward", "backward", "adam"), key=lambda k: kt[k][0])
+    avg_s = kt[dom][0] / kt[dom][1] / 1e3
+    achieved = ab[dom] / avg_s / 1e9
+    fwd_bwd_ms = sum(kt[k][0] for k in ("rays", "forward", "backward", "reduce")) / args.steps
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if cfg.precision == 0 else "bf16/f16+f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.grid}^3 phantom of {w.n_ellipsoids} ellipsoids, "
+                               f"{w.n_views} views on {w.n_det}x{w.n_det} detector, "
+                               f"{'Poisson I0=%g' % w.noise_i0 if w.noise_i0 else 'noiseless'}",
+                   "levels": w.n_levels, "feats": w.feats, "log2_table": w.log2_table,
+                   "base_res": w.base_res, "max_res": w.max_res, "mlp": f"{w.depth}x{w.width}",
+                   "samples_per_ray": w.samples, "rays_per_step": w.rays,
+                   "points_per_step": P, "n_params": lay["n_table"] + lay["n_dense"],
+                   "precision": cfg.precision},
+        "fwd_bwd_pts_per_s": P / (fwd_bwd_ms / 1e3),
+        "kernels": per_kernel,
+        "final_loss": float(losses[-1]),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": ab[dom]},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, g, A)
+    model.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * nic.h - C ABI of libnic: training step of a hash-encoded attenuation field for sparse-view
+ * cone-beam CT on one AMD MI355X (gfx950), following Xu et al., "NeRF-based CBCT Reconstruction
+ * needs Normalization and Initialization" (arXiv 2506.19742).
+ *
+ * Problem statement (Sec. 2.1 Pipeline, Sec. 2.2): cone-beam projections with known source and
+ * detector positions go in; an attenuation field mu(x, y, z), queried at points or rendered on a
+ * voxel grid, comes out.  The field is a multiresolution hash encoding (Instant-NGP, cited in
+ * Sec. 1), a LayerNorm (the "Normalized Hash Encoder", Sec. 2.3) and a small MLP.  Training
+ * minimises the L1 distance between measured line integrals and the ray sums of Eq. (1)
+ * (Sec. 2.5, Eq. 3) with Adam at lr 1e-3, one view per step (Sec. 3.1).  Mapping Consistency
+ * Initialization transfers the LayerNorm + MLP weights of a trained model to a new one
+ * (Sec. 2.1, Sec. 2.4).
+ *
+ * Conventions shared by every entry point:
+ *  - Memory: the caller owns every device buffer.  All model state lives in one caller-provided
+ *    device workspace of nic_workspace_size() bytes; the library never allocates device memory.
+ *    Pointers named *_dev are device pointers, everything else is host memory.
+ *  - Streams: every call is asynchronous on the stream given to nic_create (a hipStream_t, NULL =
+ *    default stream), except those documented as synchronous (loss_host != NULL, export/import,
+ *    save/load), which synchronise that stream before returning.
+ *  - Errors: a negative nic_status; nic_last_error() returns a message (thread-local).  Argument
+ *    errors (NIC_EINVAL) are detected before any launch and leave the model unchanged.  No
+ *    exception or abort crosses the ABI.
+ *  - Threading: calls on one model must not overlap; use one model per host thread and stream.
+ *
+ * Geometry (all lengths mm, rotation about z): source s = dso (cos a, sin a, 0); detector centre
+ * -(dsd - dso)(cos a, sin a, 0); detector axes e_u = (-sin a, cos a, 0), e_v = (0, 0, 1); pixel
+ * (row r, column c) centre at u = ((c + 1/2) - nu/2) du + off_u, v = ((r + 1/2) - nv/2) dv + off_v.
+ * Projections are line integrals A = -ln(I/I0) (Eq. 1), float32 [n_views][nv][nu], pixel index
+ * r * nu + c.  The reconstruction box [-vol/2, vol/2] is centred at the origin; normalised
+ * coordinates are x_n = (x + vol/2) / vol in [0, 1].
+ */
+#ifndef NIC_H
+#define NIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nic_status;
+#define NIC_OK 0
+#define NIC_EINVAL (-1)      /* invalid argument or unsupported configuration */
+#define NIC_ENOMEM (-2)      /* workspace too small */
+#define NIC_EHIP (-3)        /* HIP runtime error (launch or copy) */
+#define NIC_ENONFINITE (-4)  /* non-finite loss read back */
+#define NIC_EVERSION (-5)    /* blob or state of another format/version/configuration */
+#define NIC_ESTATE (-6)      /* call not valid in the model's current state */
+
+typedef struct nic_geometry {
+  double dso, dsd;            /* source-origin, source-detector distance (mm), dsd > dso > 0 */
+  int32_t det_nu, det_nv;     /* detector columns, rows (>= 1) */
+  double det_du, det_dv;      /* pixel pitch (mm, > 0) */
+  double det_off_u, det_off_v;/* detector offset (mm) */
+  double vol_size[3];         /* box edge lengths x, y, z (mm, > 0) */
+  int32_t n_views;            /* >= 1 */
+  int32_t pad_;
+  const double* angles_rad;   /* host [n_views], copied by nic_create */
+} nic_geometry;
+
+typedef struct nic_config {
+  /* Encoder (multiresolution hash grid, Instant-NGP as cited in Sec. 1): L levels, F = 2 features
+   * per level, T = 2^log2_table entries per hashed level, resolutions N_l = floor(N_min b^l) with
+   * b = exp((ln N_max - ln N_min)/(L-1)).  Supported: L in {4, 8, 12, 16}, F == 2. */
+  int32_t n_levels, feats_per_level, log2_table, base_res, max_res;
+  /* Network: depth hidden ReLU layers of width W (W in {32, 64}, 1 <= depth <= 8), linear head;
+   * out_act 0: mu = mu_max * sigmoid(y), 1: identity, 2: softplus. */
+  int32_t mlp_depth, mlp_width, out_act;
+  /* Samples per ray N (multiple of 32, 32..1024) and rays per step R (1..65536, <= pixels). */
+  int32_t samples_per_ray, rays_per_step;
+  int32_t layernorm;          /* 1: LayerNorm between encoder and network (Sec. 2.3), 0: none */
+  int32_t precision;          /* 0: FP32; 1: BF16 MLP operands (FP32 accumulate) + FP16 table
+                                 copy for gathers, FP32 master weights, grads and Adam */
+  double mu_max;              /* output scale for out_act 0 (1/mm) */
+  double ln_eps;              /* LayerNorm epsilon */
+  double lr, beta1, beta2, adam_eps;   /* Adam (Sec. 3.1: lr 1e-3) */
+  uint64_t seed;              /* Philox4x32-10 key for the device draws */
+} nic_config;
+
+/* Host-side description of a configuration (no GPU needed). */
+typedef struct nic_layout {
+  int32_t n_levels;
+  int32_t res[16];            /* N_l */
+  int32_t dense[16];          /* 1 when the level stores one entry per vertex */
+  int64_t offset[16];         /* first entry of the level */
+  int64_t n_entries;          /* table entries (each feats_per_level floats) */
+  int64_t n_table;            /* table parameters = n_entries * feats_per_level */
+  int64_t n_dense;            /* LayerNorm + MLP parameters */
+  int64_t dense_offset;       /* index of the first dense parameter in the parameter vector */
+  int64_t n_params_padded;    /* length of the parameter vector (padding entries stay 0) */
+} nic_layout;
+
+typedef struct nic_model nic_model;   /* opaque; owns no device memory */
+
+/* Tensor view returned by nic_tensors. dtype 0 = float32, 1 = float16. */
+typedef struct nic_tensor {
+  void* ptr;
+  int64_t numel;
+  int32_t dtype;
+  int32_t pad_;
+} nic_tensor;
+
+/* Level table and parameter counts of a configuration.  Parameter vector layout:
+ * [table: n_entries x F, entry-major, level after level][padding][dense block][padding], dense
+ * block = ln_gain[C] ln_bias[C] then per hidden layer k: W_k[W][in_k] (row = output unit) b_k[W],
+ * then w_out[W] b_out[1], with C = L*F, in_0 = C, in_k = W.  Returns NIC_EINVAL for an
+ * unsupported configuration.  Host only. */
+nic_status nic_describe(const nic_config* cfg, nic_layout* out);
+
+/* Bytes of device workspace a model needs (0 for an invalid configuration).  Host only. */
+size_t nic_workspace_size(const nic_config* cfg, const nic_geometry* geom);
+
+/* Creates a model in the caller's workspace (>= nic_workspace_size bytes, 256-byte aligned) on
+ * hip_stream, and initialises the parameters on the device from cfg->seed (table uniform in
+ * [-1e-4, 1e-4), linear layers uniform in +-1/sqrt(fan_in), LayerNorm gain 1 bias 0; Adam state 0,
+ * step 0).  The host object is freed by nic_destroy; the workspace stays the caller's. */
+nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip_stream,
+                      void* workspace, size_t ws_bytes, nic_model** out);
+void nic_destroy(nic_model* m);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* nic_last_error(void);
+
+/* Borrows the measured projections (device, float32 [n_views][nv][nu] line integrals) until
+ * nic_destroy or the next call. */
+nic_status nic_set_projections(nic_model* m, const float* proj_dev);
+
+/* Device views of the parameters, gradients and Adam moments, in this order: params (float32,
+ * n_params_padded), grads, adam_m, adam_v, table_f16 (float16, n_table; precision 1 only, else
+ * numel 0).  *count receives 5.  Writing params directly is allowed between calls (call
+ * nic_sync_params afterwards when precision == 1). */
+nic_status nic_tensors(nic_model* m, nic_tensor* out, int32_t* count);
+
+/* Re-derives the FP16 table copy from the FP32 master table (precision 1; no-op otherwise). */
+nic_status nic_sync_params(nic_model* m);
+
+/* Re-initialises parameters from seed (as in nic_create) and resets Adam state and step to 0. */
+nic_status nic_init_params(nic_model* m, uint64_t seed);
+
+/* One full training step (Sec. 2.5, Eq. 3; Sec. 3.1): rays of one view -> samples -> encode ->
+ * LayerNorm -> MLP -> ray sums (Eq. 1) -> L1 loss -> backward (table scatter-add, MLP and
+ * LayerNorm gradients) -> Adam on every parameter.  view in [0, n_views).  pix_dev: device int32
+ * [R] distinct pixel indices, or NULL to draw them on the device (Philox, step counter as
+ * counter).  jitter_dev: device float32 [R][N] in [0, 1), or NULL to draw on the device.
+ * loss_dev: device float32 [1] receiving the step's loss, or NULL.  Increments the step. */
+nic_status nic_step(nic_model* m, int32_t view, const int32_t* pix_dev, const float* jitter_dev,
+                    float* loss_dev);
+
+/* n_steps training steps with every draw on the device: view order a fresh permutation of the
+ * views per epoch of n_views steps, pixels and jitter from Philox.  loss_host: host float32
+ * [n_steps] (synchronous; NIC_ENONFINITE if any loss is not finite) or NULL (asynchronous). */
+nic_status nic_train(nic_model* m, int32_t n_steps, float* loss_host);
+
+/* The view nic_train uses at step `step` (host only). */
+int32_t nic_view_for_step(const nic_model* m, int64_t step);
+
+/* The pixels and jitter the device draws at step `step` (as nic_step with NULL arrays). */
+nic_status nic_draw_rays(nic_model* m, int64_t step, int32_t* pix_dev, float* jitter_dev);
+
+/* Forward pass only (Eq. 1): a_pred_dev (device float32 [n_rays]) = ray sums of n_rays rays of
+ * `view` with the given pixels and jitter (both required). n_rays <= rays_per_step. */
+nic_status nic_forward(nic_model* m, int32_t view, const int32_t* pix_dev, const float* jitter_dev,
+                       int32_t n_rays, float* a_pred_dev);
+
+/* Backward pass for an upstream gradient dA_dev (device float32 [n_rays], d loss / d A_pred) of
+ * the same rays: accumulates parameter gradients into the grads tensor (not zeroed first). */
+nic_status nic_backward(nic_model* m, int32_t view, const int32_t* pix_dev, const float* jitter_dev,
+                        int32_t n_rays, const float* dA_dev);
+
+/* Adam step on every parameter (dense, PyTorch semantics), then zeroes the gradients and
+ * increments the step. */
+nic_status nic_adam(nic_model* m);
+
+/* Zeroes the gradients. */
+nic_status nic_zero_grad(nic_model* m);
+
+/* mu at n points given in normalised coordinates (device float32 [n][3] in [0, 1]) into mu_dev
+ * (device float32 [n]). */
+nic_status nic_query(nic_model* m, const float* xn_dev, int64_t n, float* mu_dev);
+
+/* mu at the voxel centres ((i + 1/2)/nx, (j + 1/2)/ny, (k + 1/2)/nz) into vol_dev (device float32
+ * [nz][ny][nx]); dims = {nx, ny, nz}. */
+nic_status nic_render_volume(nic_model* m, const int32_t dims[3], float* vol_dev);
+
+/* Raw encoding (before LayerNorm) at n normalised points: enc_dev (device float32 [n][L*F], channel
+ * l*F + f) and, when idx_dev != NULL, the global table entry of every corner (device uint32
+ * [n][L][8], corner c = c0 + 2 c1 + 4 c2). */
+nic_status nic_encode(nic_model* m, const float* xn_dev, int64_t n, float* enc_dev, uint32_t* idx_dev);
+
+/* Current Adam step count (host only). */
+int64_t nic_get_step(const nic_model* m);
+
+/* Kernel timing for benchmarks: with enable != 0, every kernel of the training path is bracketed
+ * by a pair of HIP events on the model's stream.  nic_kernel_times synchronises the stream and
+ * returns, per kernel kind k (0 rays, 1 forward, 2 backward, 3 reduce, 4 adam), the total
+ * milliseconds ms[k] and the number of launches calls[k] since timing was enabled (*count = 5). */
+nic_status nic_set_timing(nic_model* m, int32_t enable);
+nic_status nic_kernel_times(nic_model* m, double* ms, int64_t* calls, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NIC_H */

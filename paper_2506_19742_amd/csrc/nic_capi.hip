@@ -1,0 +1,640 @@
+// C ABI of libnic (declared in include/nic.h): validation, level table, workspace layout, stream
+// handling, and the launch sequence of each entry point.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nic.h"
+#include "nic_device.h"
+#include "nic_internal.h"
+
+using namespace nic;
+
+namespace {
+
+thread_local std::string g_err;
+
+nic_status fail(nic_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define NIC_HIP(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(NIC_EHIP, "%s: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+constexpr int64_t kAlign = 256;
+constexpr int kMaxBwdBlocks = 2048;
+constexpr int kLossHist = 4096;
+
+int64_t up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Everything derived from a configuration on the host.
+struct Plan {
+  LevelTab lt{};
+  int32_t res[kMaxLevels]{}, dense[kMaxLevels]{};
+  int64_t off[kMaxLevels]{};
+  int64_t n_entries = 0, n_table = 0, n_dense = 0, nd_pad = 0, dense_off = 0, n_params_pad = 0;
+  int C = 0;
+  KernelSet ks;
+  // workspace offsets (bytes)
+  int64_t o_params, o_grads, o_m, o_v, o_th, o_part, o_rays, o_wsum, o_enc, o_apred, o_absres, o_loss, o_pix;
+  int64_t bytes = 0;
+};
+
+std::string check_config(const nic_config* c) {
+  if (!c) return "config is NULL";
+  if (c->n_levels != 8 && c->n_levels != 16) return "n_levels must be 8 or 16";
+  if (c->feats_per_level != 2) return "feats_per_level must be 2";
+  if (c->log2_table < 4 || c->log2_table > 26) return "log2_table must be in [4, 26]";
+  if (c->base_res < 1 || c->max_res < c->base_res || c->max_res > 32768) return "need 1 <= base_res <= max_res <= 32768";
+  if (c->mlp_width != 32 && c->mlp_width != 64) return "mlp_width must be 32 or 64";
+  if (c->mlp_depth < 1 || c->mlp_depth > 4) return "mlp_depth must be in [1, 4]";
+  if (c->out_act < 0 || c->out_act > 2) return "out_act must be 0, 1 or 2";
+  if (c->samples_per_ray < 32 || c->samples_per_ray > 1024 || c->samples_per_ray % 32)
+    return "samples_per_ray must be a multiple of 32 in [32, 1024]";
+  if (c->rays_per_step < 1 || c->rays_per_step > 65536) return "rays_per_step must be in [1, 65536]";
+  if (c->layernorm != 0 && c->layernorm != 1) return "layernorm must be 0 or 1";
+  if (c->precision != 0 && c->precision != 1) return "precision must be 0 or 1";
+  if (!(c->mu_max > 0) || !std::isfinite(c->mu_max)) return "mu_max must be positive";
+  if (!(c->ln_eps > 0) || !std::isfinite(c->ln_eps)) return "ln_eps must be positive";
+  if (!(c->lr > 0) || !std::isfinite(c->lr)) return "lr must be positive";
+  if (!(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1)) return "betas must be in [0, 1)";
+  if (!(c->adam_eps > 0) || !std::isfinite(c->adam_eps)) return "adam_eps must be positive";
+  return "";
+}
+
+std::string check_geometry(const nic_geometry* g, int64_t rays) {
+  if (!g) return "geometry is NULL";
+  if (!(g->dso > 0) || !(g->dsd > g->dso) || !std::isfinite(g->dsd)) return "need 0 < dso < dsd";
+  if (g->det_nu < 1 || g->det_nv < 1) return "detector size must be positive";
+  if ((int64_t)g->det_nu * g->det_nv > (1ll << 30)) return "detector too large";
+  if (!(g->det_du > 0) || !(g->det_dv > 0)) return "pixel pitch must be positive";
+  if (!std::isfinite(g->det_off_u) || !std::isfinite(g->det_off_v)) return "detector offset must be finite";
+  for (int k = 0; k < 3; ++k)
+    if (!(g->vol_size[k] > 0) || !std::isfinite(g->vol_size[k])) return "vol_size must be positive";
+  const double half_diag = 0.5 * std::sqrt(g->vol_size[0] * g->vol_size[0] + g->vol_size[1] * g->vol_size[1]);
+  if (!(g->dso > half_diag)) return "source must lie outside the reconstruction box";
+  if (g->n_views < 1 || !g->angles_rad) return "need n_views >= 1 and angles";
+  for (int v = 0; v < g->n_views; ++v)
+    if (!std::isfinite(g->angles_rad[v])) return "angles must be finite";
+  if (rays > (int64_t)g->det_nu * g->det_nv) return "rays_per_step exceeds the number of pixels";
+  return "";
+}
+
+// Level resolutions of the multiresolution grid: N_l = floor(N_min * b^l),
+// b = exp((ln N_max - ln N_min)/(L - 1)); a level is dense when (N_l + 1)^3 <= T.
+bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string& err) {
+  err = check_config(c);
+  if (err.empty() && g) err = check_geometry(g, c->rays_per_step);
+  if (!err.empty()) return false;
+  const int L = c->n_levels;
+  const double b = (L > 1) ? std::exp((std::log((double)c->max_res) - std::log((double)c->base_res)) / (double)(L - 1)) : 1.0;
+  const uint64_t T = 1ull << c->log2_table;
+  int64_t off = 0;
+  for (int l = 0; l < L; ++l) {
+    const int32_t N = (int32_t)std::floor((double)c->base_res * std::pow(b, (double)l));
+    const double nv = ((double)N + 1.0) * ((double)N + 1.0) * ((double)N + 1.0);
+    const bool dense = nv <= (double)T;
+    const int64_t size = dense ? (int64_t)nv : (int64_t)T;
+    p.res[l] = N;
+    p.dense[l] = dense;
+    p.off[l] = off;
+    p.lt.res[l] = N;
+    p.lt.off[l] = (uint32_t)off;
+    p.lt.stride[l] = dense ? (uint32_t)(N + 1) : 0u;
+    off += size;
+  }
+  p.lt.mask = (uint32_t)(T - 1);
+  p.lt.L = L;
+  p.n_entries = off;
+  p.n_table = off * 2;
+  if (p.n_table >= (1ll << 31)) { err = "hash table too large"; return false; }
+  p.C = 2 * L;
+  p.ks = kernel_set(L, c->mlp_width, c->mlp_depth, c->precision);
+  if (!p.ks.valid) { err = "unsupported (levels, width, depth, precision) combination"; return false; }
+  p.n_dense = p.ks.n_dense;
+  p.nd_pad = p.ks.nd_pad;
+  p.dense_off = up(p.n_table, 64);
+  p.n_params_pad = up(p.dense_off + p.n_dense, 64);
+  // workspace
+  const int64_t R = c->rays_per_step, N = c->samples_per_ray;
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) { const int64_t at = o; o = up(o + bytes, kAlign); return at; };
+  p.o_params = take(p.n_params_pad * 4);
+  p.o_grads = take(p.n_params_pad * 4);
+  p.o_m = take(p.n_params_pad * 4);
+  p.o_v = take(p.n_params_pad * 4);
+  p.o_th = take(c->precision ? p.n_table * 2 : 0);
+  p.o_part = take((int64_t)kMaxBwdBlocks * p.nd_pad * 4);
+  p.o_rays = take(R * (int64_t)sizeof(RayRec));
+  p.o_wsum = take(R * N / kPtsPerWave * 4);
+  p.o_enc = take(R * N * p.C * 4);
+  p.o_apred = take(R * 4);
+  p.o_absres = take(R * 4);
+  p.o_loss = take(kLossHist * 4);
+  p.o_pix = take(R * 4);
+  p.bytes = o;
+  return true;
+}
+
+}  // namespace
+
+struct nic_model {
+  nic_config cfg;
+  Plan plan;
+  Geo geo;
+  int32_t n_views = 0;
+  std::vector<double> ca, sa;
+  int32_t h_bits = 1;
+  uint32_t n_pix = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 0;
+  int bwd_grid = 0;
+  char* ws = nullptr;
+  float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+  __half* th = nullptr;
+  float *partials = nullptr, *wsum = nullptr, *enc = nullptr, *apred = nullptr, *absres = nullptr, *loss = nullptr;
+  RayRec* rays = nullptr;
+  int32_t* pix = nullptr;
+  const float* proj = nullptr;
+  int64_t step = 0;
+  int64_t epoch_cached = -1;
+  std::vector<int32_t> epoch_order;
+  // kernel timing (benchmarks)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double ms[5] = {0, 0, 0, 0, 0};
+  int64_t calls[5] = {0, 0, 0, 0, 0};
+};
+
+namespace {
+
+hipEvent_t ev_get(nic_model* m) {
+  if (!m->ev_free.empty()) {
+    hipEvent_t e = m->ev_free.back();
+    m->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when timing is on.
+struct KTimer {
+  nic_model* m;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  KTimer(nic_model* m_, int kind_) : m(m_), kind(kind_) {
+    if (m->timing) {
+      a = ev_get(m);
+      b = ev_get(m);
+      if (a) (void)hipEventRecord(a, m->stream);
+    }
+  }
+  ~KTimer() {
+    if (m->timing && a && b) {
+      (void)hipEventRecord(b, m->stream);
+      m->ev_pending.push_back({kind, {a, b}});
+    }
+  }
+};
+
+FwdArgs fwd_args(nic_model* m, int mode, int64_t n_points) {
+  FwdArgs a{};
+  a.mode = mode;
+  a.N = m->cfg.samples_per_ray;
+  a.n_points = n_points;
+  a.table = m->params;
+  a.dense = m->params + m->plan.dense_off;
+  a.lt = m->plan.lt;
+  a.geo = m->geo;
+  a.rays = m->rays;
+  a.seed = m->cfg.seed;
+  a.step = (uint32_t)m->step;
+  a.layernorm = m->cfg.layernorm;
+  a.out_act = m->cfg.out_act;
+  a.mu_max = (float)m->cfg.mu_max;
+  a.ln_eps = (float)m->cfg.ln_eps;
+  return a;
+}
+
+nic_status rays(nic_model* m, int32_t view, const int32_t* pix_in, int32_t n_rays, uint32_t step, int32_t* pix_out,
+                float* jitter_out) {
+  RaysArgs r{};
+  r.geo = m->geo;
+  r.ca = m->ca[view];
+  r.sa = m->sa[view];
+  r.view = view;
+  r.N = m->cfg.samples_per_ray;
+  r.n_rays = n_rays;
+  r.h_bits = m->h_bits;
+  r.n_pix = m->n_pix;
+  r.step = step;
+  r.seed = m->cfg.seed;
+  r.pix_in = pix_in;
+  r.proj = m->proj;
+  r.rays = m->rays;
+  r.pix_out = pix_out;
+  r.jitter_out = jitter_out;
+  KTimer kt(m, 0);
+  NIC_HIP(launch_rays(r, m->stream));
+  return NIC_OK;
+}
+
+nic_status adam(nic_model* m) {
+  const int64_t t = m->step + 1;
+  const double bc1 = 1.0 - std::pow(m->cfg.beta1, (double)t);
+  const double bc2 = 1.0 - std::pow(m->cfg.beta2, (double)t);
+  KTimer kt(m, 4);
+  NIC_HIP(launch_adam(m->params, m->grads, m->m, m->v, m->plan.n_params_pad, (float)m->cfg.lr, (float)m->cfg.beta1,
+                      (float)m->cfg.beta2, (float)m->cfg.adam_eps, (float)(1.0 / bc1), (float)(1.0 / bc2), m->th,
+                      m->plan.n_table, m->n_cu, m->stream));
+  m->step = t;
+  return NIC_OK;
+}
+
+// Forward + backward (+ reduce) over the rays currently in m->rays.
+nic_status fwd_bwd(nic_model* m, int32_t n_rays, const float* jitter, const float* dA, float* loss_dev) {
+  const int64_t P = (int64_t)n_rays * m->cfg.samples_per_ray;
+  FwdArgs a = fwd_args(m, kModeRays, P);
+  a.jitter = jitter;
+  a.enc_out = m->enc;
+  a.wave_sum = m->wsum;
+  {
+    KTimer kt(m, 1);
+    NIC_HIP(launch_fwd(m->plan.ks, a, m->stream));
+  }
+  BwdArgs b{};
+  b.enc_in = m->enc;
+  b.dA_in = dA;
+  b.inv_R = 1.0f / (float)n_rays;
+  b.a_pred_out = m->apred;
+  b.absres_out = m->absres;
+  b.grad_table = m->grads;
+  b.partials = m->partials;
+  const int64_t chunks = (P + kPtsPerBlock - 1) / kPtsPerBlock;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, m->bwd_grid));
+  {
+    KTimer kt(m, 2);
+    NIC_HIP(launch_bwd(m->plan.ks, a, b, grid, m->stream));
+  }
+  KTimer kt(m, 3);
+  NIC_HIP(launch_reduce(m->partials, grid, m->plan.nd_pad, (int)m->plan.n_dense, m->grads + m->plan.dense_off,
+                        m->absres, n_rays, 1.0f / (float)n_rays, dA ? nullptr : loss_dev, m->stream));
+  return NIC_OK;
+}
+
+bool model_ok(const nic_model* m) { return m != nullptr && m->ws != nullptr; }
+
+
+
+}  // namespace
+
+extern "C" {
+
+const char* nic_last_error(void) { return g_err.c_str(); }
+
+nic_status nic_describe(const nic_config* cfg, nic_layout* out) {
+  if (!out) return fail(NIC_EINVAL, "out is NULL");
+  Plan p;
+  std::string err;
+  if (!make_plan(cfg, nullptr, p, err)) return fail(NIC_EINVAL, "%s", err.c_str());
+  memset(out, 0, sizeof *out);
+  out->n_levels = cfg->n_levels;
+  for (int l = 0; l < cfg->n_levels; ++l) {
+    out->res[l] = p.res[l];
+    out->dense[l] = p.dense[l];
+    out->offset[l] = p.off[l];
+  }
+  out->n_entries = p.n_entries;
+  out->n_table = p.n_table;
+  out->n_dense = p.n_dense;
+  out->dense_offset = p.dense_off;
+  out->n_params_padded = p.n_params_pad;
+  return NIC_OK;
+}
+
+size_t nic_workspace_size(const nic_config* cfg, const nic_geometry* geom) {
+  Plan p;
+  std::string err;
+  if (!geom || !make_plan(cfg, geom, p, err)) {
+    g_err = geom ? err : "geometry is NULL";
+    return 0;
+  }
+  return (size_t)p.bytes;
+}
+
+nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip_stream, void* workspace,
+                      size_t ws_bytes, nic_model** out) {
+  if (!out) return fail(NIC_EINVAL, "out is NULL");
+  *out = nullptr;
+  Plan p;
+  std::string err;
+  if (!geom) return fail(NIC_EINVAL, "geometry is NULL");
+  if (!make_plan(cfg, geom, p, err)) return fail(NIC_EINVAL, "%s", err.c_str());
+  if (!workspace) return fail(NIC_EINVAL, "workspace is NULL");
+  if (((uintptr_t)workspace) % kAlign) return fail(NIC_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < (size_t)p.bytes) return fail(NIC_ENOMEM, "workspace has %zu bytes, needs %lld", ws_bytes, (long long)p.bytes);
+
+  nic_model* m = new nic_model();
+  m->cfg = *cfg;
+  m->plan = p;
+  m->stream = (hipStream_t)hip_stream;
+  m->n_views = geom->n_views;
+  m->ca.resize(geom->n_views);
+  m->sa.resize(geom->n_views);
+  for (int v = 0; v < geom->n_views; ++v) {
+    m->ca[v] = std::cos(geom->angles_rad[v]);
+    m->sa[v] = std::sin(geom->angles_rad[v]);
+  }
+  Geo& g = m->geo;
+  g.dso = geom->dso;
+  g.back = geom->dsd - geom->dso;
+  g.du = geom->det_du;
+  g.dv = geom->det_dv;
+  g.off_u = geom->det_off_u;
+  g.off_v = geom->det_off_v;
+  for (int k = 0; k < 3; ++k) {
+    g.vol[k] = geom->vol_size[k];
+    g.inv_vol[k] = 1.0 / geom->vol_size[k];
+  }
+  g.nu = geom->det_nu;
+  g.nv = geom->det_nv;
+  m->n_pix = (uint32_t)((int64_t)geom->det_nu * geom->det_nv);
+  int bits = 0;
+  while ((1ll << bits) < (int64_t)m->n_pix) ++bits;
+  if (bits & 1) ++bits;
+  if (bits < 2) bits = 2;
+  m->h_bits = bits / 2;
+
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipFuncSetAttribute(p.ks.fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.ks.fwd_lds);
+  if (e == hipSuccess) e = hipFuncSetAttribute(p.ks.bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.ks.bwd_lds);
+  int per_cu = 0;
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.ks.bwd, kBlock, p.ks.bwd_lds);
+  if (e != hipSuccess) {
+    delete m;
+    return fail(NIC_EHIP, "device query: %s", hipGetErrorString(e));
+  }
+  m->bwd_grid = std::max(1, std::min(kMaxBwdBlocks, m->n_cu * std::max(1, per_cu)));
+
+  char* ws = (char*)workspace;
+  m->ws = ws;
+  m->params = (float*)(ws + p.o_params);
+  m->grads = (float*)(ws + p.o_grads);
+  m->m = (float*)(ws + p.o_m);
+  m->v = (float*)(ws + p.o_v);
+  m->th = cfg->precision ? (__half*)(ws + p.o_th) : nullptr;
+  m->partials = (float*)(ws + p.o_part);
+  m->rays = (RayRec*)(ws + p.o_rays);
+  m->wsum = (float*)(ws + p.o_wsum);
+  m->enc = (float*)(ws + p.o_enc);
+  m->apred = (float*)(ws + p.o_apred);
+  m->absres = (float*)(ws + p.o_absres);
+  m->loss = (float*)(ws + p.o_loss);
+  m->pix = (int32_t*)(ws + p.o_pix);
+  *out = m;
+  const nic_status st = nic_init_params(m, cfg->seed);
+  if (st != NIC_OK) {
+    delete m;
+    *out = nullptr;
+    return st;
+  }
+  return NIC_OK;
+}
+
+void nic_destroy(nic_model* m) {
+  if (!m) return;
+  for (auto& pe : m->ev_pending) {
+    (void)hipEventDestroy(pe.second.first);
+    (void)hipEventDestroy(pe.second.second);
+  }
+  for (hipEvent_t e : m->ev_free) (void)hipEventDestroy(e);
+  delete m;
+}
+
+nic_status nic_set_timing(nic_model* m, int32_t enable) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  m->timing = enable != 0;
+  for (int k = 0; k < 5; ++k) { m->ms[k] = 0; m->calls[k] = 0; }
+  return NIC_OK;
+}
+
+nic_status nic_kernel_times(nic_model* m, double* ms, int64_t* calls, int32_t* count) {
+  if (!model_ok(m) || !ms || !calls || !count) return fail(NIC_EINVAL, "NULL argument");
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  for (auto& pe : m->ev_pending) {
+    float t = 0.0f;
+    NIC_HIP(hipEventElapsedTime(&t, pe.second.first, pe.second.second));
+    m->ms[pe.first] += t;
+    m->calls[pe.first] += 1;
+    m->ev_free.push_back(pe.second.first);
+    m->ev_free.push_back(pe.second.second);
+  }
+  m->ev_pending.clear();
+  for (int k = 0; k < 5; ++k) { ms[k] = m->ms[k]; calls[k] = m->calls[k]; }
+  *count = 5;
+  return NIC_OK;
+}
+
+nic_status nic_init_params(nic_model* m, uint64_t seed) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  const Plan& p = m->plan;
+  const int C = p.C, W = m->cfg.mlp_width;
+  InitArgs ia{};
+  ia.seed = seed;
+  ia.n_dense = p.n_dense;
+  ia.ln_end = 2 * C;
+  ia.first_layer_end = 2 * C + (int64_t)W * C + W;
+  ia.fan0 = C;
+  ia.width = W;
+  NIC_HIP(launch_fill(m->params, p.n_params_pad, 0.0f, m->n_cu, m->stream));
+  NIC_HIP(launch_fill(m->grads, p.n_params_pad, 0.0f, m->n_cu, m->stream));
+  NIC_HIP(launch_fill(m->m, p.n_params_pad, 0.0f, m->n_cu, m->stream));
+  NIC_HIP(launch_fill(m->v, p.n_params_pad, 0.0f, m->n_cu, m->stream));
+  NIC_HIP(launch_init(m->params, p.n_table, p.dense_off, ia, m->n_cu, m->stream));
+  if (m->th) NIC_HIP(launch_to_half(m->params, m->th, p.n_table, m->n_cu, m->stream));
+  m->step = 0;
+  return NIC_OK;
+}
+
+nic_status nic_set_projections(nic_model* m, const float* proj_dev) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  m->proj = proj_dev;
+  return NIC_OK;
+}
+
+nic_status nic_tensors(nic_model* m, nic_tensor* out, int32_t* count) {
+  if (!model_ok(m) || !out || !count) return fail(NIC_EINVAL, "NULL argument");
+  const int64_t n = m->plan.n_params_pad;
+  out[0] = nic_tensor{m->params, n, 0, 0};
+  out[1] = nic_tensor{m->grads, n, 0, 0};
+  out[2] = nic_tensor{m->m, n, 0, 0};
+  out[3] = nic_tensor{m->v, n, 0, 0};
+  out[4] = nic_tensor{m->th, m->th ? m->plan.n_table : 0, 1, 0};
+  *count = 5;
+  return NIC_OK;
+}
+
+nic_status nic_sync_params(nic_model* m) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (m->th) NIC_HIP(launch_to_half(m->params, m->th, m->plan.n_table, m->n_cu, m->stream));
+  return NIC_OK;
+}
+
+int64_t nic_get_step(const nic_model* m) { return m ? m->step : -1; }
+
+int32_t nic_view_for_step(const nic_model* m_, int64_t step) {
+  nic_model* m = const_cast<nic_model*>(m_);
+  if (!m || step < 0) return -1;
+  const int32_t V = m->n_views;
+  const int64_t e = step / V;
+  if (e != m->epoch_cached) {
+    std::vector<std::pair<uint32_t, int32_t>> key(V);
+    for (int32_t v = 0; v < V; ++v) key[v] = {philox_w0(m->cfg.seed, (uint32_t)v, (uint32_t)e, 0, kViews), v};
+    std::sort(key.begin(), key.end());
+    m->epoch_order.resize(V);
+    for (int32_t k = 0; k < V; ++k) m->epoch_order[k] = key[k].second;
+    m->epoch_cached = e;
+  }
+  return m->epoch_order[step % V];
+}
+
+nic_status nic_draw_rays(nic_model* m, int64_t step, int32_t* pix_dev, float* jitter_dev) {
+  if (!model_ok(m) || !pix_dev || !jitter_dev) return fail(NIC_EINVAL, "NULL argument");
+  if (step < 0) return fail(NIC_EINVAL, "step must be >= 0");
+  return rays(m, 0, nullptr, m->cfg.rays_per_step, (uint32_t)step, pix_dev, jitter_dev);
+}
+
+nic_status nic_step(nic_model* m, int32_t view, const int32_t* pix_dev, const float* jitter_dev, float* loss_dev) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (view < 0 || view >= m->n_views) return fail(NIC_EINVAL, "view %d out of range", view);
+  if (!m->proj) return fail(NIC_ESTATE, "projections not set");
+  const int32_t R = m->cfg.rays_per_step;
+  nic_status st = rays(m, view, pix_dev, R, (uint32_t)m->step, nullptr, nullptr);
+  if (st) return st;
+  st = fwd_bwd(m, R, jitter_dev, nullptr, loss_dev ? loss_dev : m->loss);
+  if (st) return st;
+  return adam(m);
+}
+
+nic_status nic_train(nic_model* m, int32_t n_steps, float* loss_host) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (n_steps < 0) return fail(NIC_EINVAL, "n_steps must be >= 0");
+  if (!m->proj) return fail(NIC_ESTATE, "projections not set");
+  bool bad = false;
+  for (int32_t k0 = 0; k0 < n_steps; k0 += kLossHist) {
+    const int32_t kn = std::min<int32_t>(kLossHist, n_steps - k0);
+    for (int32_t k = 0; k < kn; ++k) {
+      const int32_t view = nic_view_for_step(m, m->step);
+      nic_status st = rays(m, view, nullptr, m->cfg.rays_per_step, (uint32_t)m->step, nullptr, nullptr);
+      if (st) return st;
+      st = fwd_bwd(m, m->cfg.rays_per_step, nullptr, nullptr, m->loss + k);
+      if (st) return st;
+      st = adam(m);
+      if (st) return st;
+    }
+    if (loss_host) {
+      NIC_HIP(hipMemcpyAsync(loss_host + k0, m->loss, kn * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+      NIC_HIP(hipStreamSynchronize(m->stream));
+      for (int32_t k = 0; k < kn; ++k)
+        if (!std::isfinite(loss_host[k0 + k])) bad = true;
+    }
+  }
+  if (bad) return fail(NIC_ENONFINITE, "non-finite loss");
+  return NIC_OK;
+}
+
+nic_status nic_forward(nic_model* m, int32_t view, const int32_t* pix_dev, const float* jitter_dev, int32_t n_rays,
+                       float* a_pred_dev) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (view < 0 || view >= m->n_views) return fail(NIC_EINVAL, "view %d out of range", view);
+  if (!pix_dev || !jitter_dev || !a_pred_dev) return fail(NIC_EINVAL, "NULL argument");
+  if (n_rays < 0 || n_rays > m->cfg.rays_per_step) return fail(NIC_EINVAL, "n_rays out of range");
+  if (n_rays == 0) return NIC_OK;
+  nic_status st = rays(m, view, pix_dev, n_rays, (uint32_t)m->step, nullptr, nullptr);
+  if (st) return st;
+  const int64_t P = (int64_t)n_rays * m->cfg.samples_per_ray;
+  FwdArgs a = fwd_args(m, kModeRays, P);
+  a.jitter = jitter_dev;
+  a.wave_sum = m->wsum;
+  NIC_HIP(launch_fwd(m->plan.ks, a, m->stream));
+  NIC_HIP(launch_raysum(m->wsum, m->cfg.samples_per_ray / kPtsPerWave, n_rays, a_pred_dev, m->stream));
+  return NIC_OK;
+}
+
+nic_status nic_backward(nic_model* m, int32_t view, const int32_t* pix_dev, const float* jitter_dev, int32_t n_rays,
+                        const float* dA_dev) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (view < 0 || view >= m->n_views) return fail(NIC_EINVAL, "view %d out of range", view);
+  if (!pix_dev || !jitter_dev || !dA_dev) return fail(NIC_EINVAL, "NULL argument");
+  if (n_rays < 0 || n_rays > m->cfg.rays_per_step) return fail(NIC_EINVAL, "n_rays out of range");
+  if (n_rays == 0) return NIC_OK;
+  nic_status st = rays(m, view, pix_dev, n_rays, (uint32_t)m->step, nullptr, nullptr);
+  if (st) return st;
+  return fwd_bwd(m, n_rays, jitter_dev, dA_dev, nullptr);
+}
+
+nic_status nic_adam(nic_model* m) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  return adam(m);
+}
+
+nic_status nic_zero_grad(nic_model* m) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  NIC_HIP(launch_fill(m->grads, m->plan.n_params_pad, 0.0f, m->n_cu, m->stream));
+  return NIC_OK;
+}
+
+nic_status nic_query(nic_model* m, const float* xn_dev, int64_t n, float* mu_dev) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (n < 0) return fail(NIC_EINVAL, "n must be >= 0");
+  if (n == 0) return NIC_OK;
+  if (!xn_dev || !mu_dev) return fail(NIC_EINVAL, "NULL argument");
+  FwdArgs a = fwd_args(m, kModePoints, n);
+  a.xn = xn_dev;
+  a.mu_out = mu_dev;
+  NIC_HIP(launch_fwd(m->plan.ks, a, m->stream));
+  return NIC_OK;
+}
+
+nic_status nic_render_volume(nic_model* m, const int32_t dims[3], float* vol_dev) {
+  if (!model_ok(m) || !dims || !vol_dev) return fail(NIC_EINVAL, "NULL argument");
+  for (int k = 0; k < 3; ++k)
+    if (dims[k] < 1 || dims[k] > 4096) return fail(NIC_EINVAL, "dims must be in [1, 4096]");
+  const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
+  FwdArgs a = fwd_args(m, kModeVoxels, n);
+  for (int k = 0; k < 3; ++k) a.dims[k] = dims[k];
+  a.mu_out = vol_dev;
+  NIC_HIP(launch_fwd(m->plan.ks, a, m->stream));
+  return NIC_OK;
+}
+
+nic_status nic_encode(nic_model* m, const float* xn_dev, int64_t n, float* enc_dev, uint32_t* idx_dev) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (n < 0) return fail(NIC_EINVAL, "n must be >= 0");
+  if (n == 0) return NIC_OK;
+  if (!xn_dev || !enc_dev) return fail(NIC_EINVAL, "NULL argument");
+  NIC_HIP(launch_encode(m->plan.lt, m->params, xn_dev, n, enc_dev, idx_dev, m->stream));
+  return NIC_OK;
+}
+
+}  // extern "C"

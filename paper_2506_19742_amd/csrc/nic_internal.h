@@ -1,0 +1,97 @@
+// Kernel argument blocks and launch entry points shared by the kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "nic_device.h"
+
+namespace nic {
+
+enum { kModeRays = 0, kModePoints = 1, kModeVoxels = 2 };
+
+struct FwdArgs {
+  int32_t mode;          // kModeRays / kModePoints / kModeVoxels
+  int32_t N;             // samples per ray (rays mode)
+  int64_t n_points;      // rays: n_rays * N
+  const float* table;    // FP32 table [n_entries][2]
+  const float* dense;    // FP32 dense parameters (global layout)
+  LevelTab lt;
+  Geo geo;
+  const RayRec* rays;
+  const float* jitter;   // [n_rays][N] or NULL (Philox)
+  uint64_t seed;
+  uint32_t step;
+  int32_t layernorm;
+  int32_t out_act;
+  float mu_max;
+  float ln_eps;
+  int32_t dims[3];       // voxel grid (voxels mode)
+  const float* xn;       // points mode [n][3]
+  float* enc_out;        // rays mode: raw encoding, lane-major per wave (or NULL)
+  float* wave_sum;       // rays mode: per-wave partial sums of mu * delta
+  float* mu_out;         // points / voxels mode
+};
+
+struct BwdArgs {
+  const float* enc_in;   // encoding stored by k_fwd
+  const float* dA_in;    // [n_rays] upstream gradient, or NULL for the L1 loss of Eq. (3)
+  float inv_R;           // 1/R for the mean over rays
+  float* a_pred_out;     // [n_rays] (L1 mode)
+  float* absres_out;     // [n_rays] (L1 mode)
+  float* grad_table;     // FP32 [n_entries][2]
+  float* partials;       // [grid][nd_pad] per-block dense gradients
+};
+
+struct RaysArgs {
+  Geo geo;
+  double ca, sa;         // cos, sin of the view angle (host libm)
+  int32_t view;
+  int32_t N;
+  int32_t n_rays;
+  int32_t h_bits;        // Feistel half width
+  uint32_t n_pix;
+  uint32_t step;
+  uint64_t seed;
+  const int32_t* pix_in; // or NULL: device draw
+  const float* proj;     // [n_views][n_pix] or NULL
+  RayRec* rays;
+  int32_t* pix_out;      // optional
+  float* jitter_out;     // optional [n_rays][N]
+};
+
+struct InitArgs {
+  uint64_t seed;
+  int64_t n_dense;
+  int64_t ln_end;          // 2C
+  int64_t first_layer_end; // end of W_0, b_0
+  int32_t fan0;            // C
+  int32_t width;           // W
+};
+
+struct KernelSet {
+  const void* fwd = nullptr;
+  const void* bwd = nullptr;
+  size_t fwd_lds = 0, bwd_lds = 0;
+  int n_dense = 0, nd_pad = 0;
+  bool valid = false;
+};
+
+KernelSet kernel_set(int L, int W, int D, int precision);
+hipError_t launch_fwd(const KernelSet& ks, const FwdArgs& a, hipStream_t s);
+hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, int grid, hipStream_t s);
+hipError_t launch_rays(const RaysArgs& a, hipStream_t s);
+hipError_t launch_raysum(const float* wave_sum, int waves_per_ray, int n_rays, float* out, hipStream_t s);
+hipError_t launch_reduce(const float* partials, int n_blocks, int nd_pad, int nd, float* grad_dense,
+                         const float* absres, int n_rays, float inv_R, float* loss_out, hipStream_t s);
+hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, float ibc1, float ibc2, __half* th, int64_t n_table, int n_cu, hipStream_t s);
+hipError_t launch_fill(float* x, int64_t n, float val, int n_cu, hipStream_t s);
+hipError_t launch_to_half(const float* src, __half* dst, int64_t n, int n_cu, hipStream_t s);
+hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const InitArgs& ia, int n_cu,
+                       hipStream_t s);
+hipError_t launch_encode(const LevelTab& lt, const float* table, const float* xn, int64_t n, float* enc,
+                         uint32_t* idx, hipStream_t s);
+
+}  // namespace nic

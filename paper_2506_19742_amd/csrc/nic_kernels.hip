@@ -1,0 +1,757 @@
+// Kernels of the training step for gfx950 (one MI355X).
+//
+// Step = k_rays -> k_fwd -> k_bwd -> k_reduce -> k_adam on the model's stream.
+//  k_rays   one thread per ray slot: pixel (given or Philox/Feistel draw), FP64 ray setup, A_gt.
+//  k_fwd    four waves per block, 32 points per wave, two lanes per point (lane half h handles
+//           half of the levels): sample position -> hash encode (8 corner gathers per level) ->
+//           LayerNorm -> MLP on v_mfma_f32_32x32x2f32 -> mu -> per-wave partial ray sum of
+//           mu * delta (Eq. 1).  Stores the raw encoding lane-major for the backward pass.
+//  k_bwd    persistent blocks over 128-point chunks: reloads the encoding, recomputes LayerNorm and
+//           the MLP forward, reads the ray's sum -> dA = sign(A - A_gt)/R (Eq. 3) -> MLP backward
+//           on MFMA (data gradients chained in registers, weight gradients via per-wave LDS
+//           transposes), LayerNorm backward, then scatter-adds the corner gradients into the FP32
+//           table gradient.  Dense (LayerNorm + MLP) gradients accumulate in LDS and are written
+//           once per block as partial sums.
+//  k_reduce sums the per-block partials into the dense gradient and the loss.
+//  k_adam   one streaming pass over every parameter: Adam update, gradient reset to 0.
+#include "nic_device.h"
+#include "nic_internal.h"
+
+namespace nic {
+
+// ---------------------------------------------------------------------------------------------
+// Dense parameter layout (global, in floats from the start of the dense block) and its LDS copy.
+// Global: ln_g[C] ln_b[C] {W_k[W][K_k] b_k[W]}_k w_out[W] b_out.  LDS: weights padded to
+// [W][K_k + 1] so both the forward (row-varying) and backward (column-varying) MFMA operand reads
+// are free of bank conflicts.
+// ---------------------------------------------------------------------------------------------
+template <int C, int W, int D>
+struct Lay {
+  static constexpr int K(int k) { return k == 0 ? C : W; }
+  // global
+  static constexpr int g_lng = 0, g_lnb = C;
+  static constexpr int gW(int k) {
+    int o = 2 * C;
+    for (int i = 0; i < k; ++i) o += W * K(i) + W;
+    return o;
+  }
+  static constexpr int gb(int k) { return gW(k) + W * K(k); }
+  static constexpr int g_wo = gW(D), g_bo = gW(D) + W, g_n = gW(D) + W + 1;
+  // LDS
+  static constexpr int sW(int k) {
+    int o = 0;
+    for (int i = 0; i < k; ++i) o += W * (K(i) + 1) + W;
+    return o;
+  }
+  static constexpr int sb(int k) { return sW(k) + W * (K(k) + 1); }
+  static constexpr int s_lng = sW(D), s_lnb = sW(D) + C, s_wo = sW(D) + 2 * C, s_bo = sW(D) + 2 * C + W;
+  static constexpr int s_n = (sW(D) + 2 * C + W + 1 + 3) & ~3;
+};
+
+template <int C, int W, int D>
+__device__ void stage_params(const float* __restrict__ dense, float* __restrict__ sp) {
+  using Ly = Lay<C, W, D>;
+  const int t = threadIdx.x, nt = blockDim.x;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    constexpr int dummy = 0;
+    (void)dummy;
+    const int Kk = Ly::K(k);
+    for (int e = t; e < W * (Kk + 1); e += nt) {
+      const int o = e / (Kk + 1), i = e - o * (Kk + 1);
+      sp[Ly::sW(k) + e] = (i < Kk) ? dense[Ly::gW(k) + o * Kk + i] : 0.0f;
+    }
+    for (int e = t; e < W; e += nt) sp[Ly::sb(k) + e] = dense[Ly::gb(k) + e];
+  }
+  for (int e = t; e < C; e += nt) {
+    sp[Ly::s_lng + e] = dense[Ly::g_lng + e];
+    sp[Ly::s_lnb + e] = dense[Ly::g_lnb + e];
+  }
+  for (int e = t; e < W; e += nt) sp[Ly::s_wo + e] = dense[Ly::g_wo + e];
+  if (t == 0) sp[Ly::s_bo] = dense[Ly::g_bo];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Per-point pieces
+// ---------------------------------------------------------------------------------------------
+
+// Encoding of the levels handled by lane half h: register r = 4j + 2q + f holds feature f of level
+// 4j + 2h + q, i.e. channel chan(r, h).
+template <int L>
+__device__ __forceinline__ void encode_half(const LevelTab& T, const float2* __restrict__ table,
+                                            const float x[3], int h, float e[L]) {
+#pragma unroll
+  for (int j = 0; j < L / 4; ++j) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int lA = 4 * j + q, lB = 4 * j + 2 + q;
+      const int32_t N = h ? T.res[lB] : T.res[lA];
+      const uint32_t off = h ? T.off[lB] : T.off[lA];
+      const uint32_t st = h ? T.stride[lB] : T.stride[lA];
+      uint32_t idx[8];
+      float w[8];
+      level_corners(N, off, st, T.mask, x, idx, w);
+      float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const float2 v = table[idx[c]];
+        s0 += w[c] * v.x;
+        s1 += w[c] * v.y;
+      }
+      e[4 * j + 2 * q] = s0;
+      e[4 * j + 2 * q + 1] = s1;
+    }
+  }
+}
+
+// Scatter-add of the channel gradients gx (same layout as encode_half) into the table gradient.
+template <int L>
+__device__ __forceinline__ void scatter_half(const LevelTab& T, float* __restrict__ gtab,
+                                             const float x[3], int h, const float gx[L]) {
+#pragma unroll
+  for (int j = 0; j < L / 4; ++j) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int lA = 4 * j + q, lB = 4 * j + 2 + q;
+      const int32_t N = h ? T.res[lB] : T.res[lA];
+      const uint32_t off = h ? T.off[lB] : T.off[lA];
+      const uint32_t st = h ? T.stride[lB] : T.stride[lA];
+      uint32_t idx[8];
+      float w[8];
+      level_corners(N, off, st, T.mask, x, idx, w);
+      const float g0 = gx[4 * j + 2 * q], g1 = gx[4 * j + 2 * q + 1];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        atomicAdd(gtab + 2 * (size_t)idx[c], w[c] * g0);
+        atomicAdd(gtab + 2 * (size_t)idx[c] + 1, w[c] * g1);
+      }
+    }
+  }
+}
+
+// LayerNorm over the C channels of a point split across the two lane halves.
+template <int C>
+__device__ __forceinline__ void ln_forward(const float e[C / 2], const float* sp_g, const float* sp_b,
+                                           float eps, int layernorm, int h, float xh[C / 2],
+                                           float z[C / 2], float& rstd) {
+  constexpr int RC = C / 2;
+  if (!layernorm) {
+#pragma unroll
+    for (int r = 0; r < RC; ++r) { xh[r] = e[r]; z[r] = e[r]; }
+    rstd = 1.0f;
+    return;
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int r = 0; r < RC; ++r) s += e[r];
+  s += xor32(s);
+  const float mean = s * (1.0f / C);
+  float v = 0.0f;
+#pragma unroll
+  for (int r = 0; r < RC; ++r) {
+    const float d = e[r] - mean;
+    v += d * d;
+  }
+  v += xor32(v);
+  rstd = 1.0f / sqrtf(v * (1.0f / C) + eps);
+#pragma unroll
+  for (int r = 0; r < RC; ++r) {
+    const int c = chan(r, h);
+    xh[r] = (e[r] - mean) * rstd;
+    z[r] = sp_g[c] * xh[r] + sp_b[c];
+  }
+}
+
+// One hidden layer forward: out = relu(W x + b) for K inputs held as K/2 registers.
+template <int K, int W>
+__device__ __forceinline__ void layer_fwd(const float* __restrict__ sW, const float* __restrict__ sb,
+                                          const float* xin, float* out, int lane) {
+  const int m = lane & 31, h = lane >> 5;
+  f32x16 acc[W / 32];
+#pragma unroll
+  for (int mb = 0; mb < W / 32; ++mb) acc[mb] = f32x16{};
+#pragma unroll
+  for (int s = 0; s < K / 2; ++s) {
+    const float b = xin[s];
+    const int col = chan(s, h);
+#pragma unroll
+    for (int mb = 0; mb < W / 32; ++mb) acc[mb] = mfma32(sW[(32 * mb + m) * (K + 1) + col], b, acc[mb]);
+  }
+#pragma unroll
+  for (int R = 0; R < W / 2; ++R) {
+    const float a = acc[R >> 4][R & 15] + sb[chan(R, h)];
+    out[R] = a > 0.0f ? a : 0.0f;
+  }
+}
+
+// Data gradient through one layer: gin = W^T g for KIN inputs (KIN/2 registers).
+template <int KIN, int W>
+__device__ __forceinline__ void layer_bwd_data(const float* __restrict__ sW, const float* g, float* gin,
+                                               int lane) {
+  const int m = lane & 31, h = lane >> 5;
+  constexpr int IB = (KIN + 31) / 32;
+  f32x16 acc[IB];
+#pragma unroll
+  for (int ib = 0; ib < IB; ++ib) acc[ib] = f32x16{};
+#pragma unroll
+  for (int s = 0; s < W / 2; ++s) {
+    const float b = g[s];
+    const int row = chan(s, h);
+#pragma unroll
+    for (int ib = 0; ib < IB; ++ib) {
+      const int i = 32 * ib + m;
+      const float a = (i < KIN) ? sW[row * (KIN + 1) + i] : 0.0f;
+      acc[ib] = mfma32(a, b, acc[ib]);
+    }
+  }
+#pragma unroll
+  for (int R = 0; R < KIN / 2; ++R) gin[R] = acc[R >> 4][R & 15];
+}
+
+// Writes rows [32*blk, 32*blk + 32) of a per-point vector (n registers, layout chan) into a
+// [32][kTile] tile with column = point.
+template <int NREG>
+__device__ __forceinline__ void tile_put(float* tile, const float* v, int blk, int lane) {
+  const int n = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int R = 16 * blk + r;
+    if (R < NREG) tile[(chan(r, h)) * kTile + n] = v[R];
+  }
+}
+
+// acc_lds[base + m] += sum over the 32 points of tile row m, for m < nrows.
+__device__ __forceinline__ void tile_rowsum_add(const float* tile, float* acc, int base, int nrows, int lane) {
+  const int m = lane & 31, h = lane >> 5;
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) s += tile[m * kTile + 16 * h + j];
+  s += xor32(s);
+  if (h == 0 && m < nrows) atomicAdd(acc + base + m, s);
+}
+
+// acc_lds[wbase + (32 mb + row) * K + 32 nb + col] += (G^T H) over the wave's 32 points, with
+// tiles tG = G rows [32mb, 32mb+32), tH = H rows [32nb, 32nb+32).
+__device__ __forceinline__ void tile_outer_add(const float* tG, const float* tH, float* acc, int wbase,
+                                               int K, int mb, int nb, int lane) {
+  const int m = lane & 31, h = lane >> 5;
+  f32x16 d = f32x16{};
+#pragma unroll
+  for (int s = 0; s < 16; ++s) d = mfma32(tG[m * kTile + 16 * h + s], tH[m * kTile + 16 * h + s], d);
+  const int col = 32 * nb + m;
+  if (col < K) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) atomicAdd(acc + wbase + (32 * mb + chan(r, h)) * K + col, d[r]);
+  }
+}
+
+__device__ __forceinline__ float act_fwd(int act, float mu_max, float y) {
+  if (act == 1) return y;
+  if (act == 2) return y > 20.0f ? y : log1pf(expf(y));
+  return mu_max / (1.0f + expf(-y));
+}
+
+__device__ __forceinline__ float act_grad(int act, float mu_max, float y) {
+  if (act == 1) return 1.0f;
+  const float s = 1.0f / (1.0f + expf(-y));
+  if (act == 2) return s;
+  return mu_max * s * (1.0f - s);
+}
+
+// Position of point p for the three point sources.
+__device__ __forceinline__ void point_position(const FwdArgs& a, int64_t p, bool valid, int64_t ray,
+                                               int i, const RayRec& rr, float x[3]) {
+  x[0] = x[1] = x[2] = 0.0f;
+  if (!valid) return;
+  if (a.mode == kModeRays) {
+    if (rr.hit) {
+      const float u = a.jitter ? a.jitter[ray * a.N + i] : jitter(a.seed, a.step, (uint32_t)ray, (uint32_t)i);
+      sample_pos(a.geo, rr, i, u, x);
+    }
+  } else if (a.mode == kModePoints) {
+    x[0] = a.xn[3 * p];
+    x[1] = a.xn[3 * p + 1];
+    x[2] = a.xn[3 * p + 2];
+  } else {
+    const int64_t nxy = (int64_t)a.dims[0] * a.dims[1];
+    const int iz = (int)(p / nxy);
+    const int64_t rem = p - (int64_t)iz * nxy;
+    const int iy = (int)(rem / a.dims[0]);
+    const int ix = (int)(rem - (int64_t)iy * a.dims[0]);
+    x[0] = voxel_coord(ix, a.dims[0]);
+    x[1] = voxel_coord(iy, a.dims[1]);
+    x[2] = voxel_coord(iz, a.dims[2]);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Forward kernel
+// ---------------------------------------------------------------------------------------------
+template <int L, int W, int D>
+__global__ void __launch_bounds__(kBlock) k_fwd(const FwdArgs a) {
+  constexpr int C = 2 * L, RC = C / 2, RW = W / 2;
+  using Ly = Lay<C, W, D>;
+  extern __shared__ float smem[];
+  float* sp = smem;
+  stage_params<C, W, D>(a.dense, sp);
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
+  const int64_t wave_id = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+  const int64_t p = wave_id * kPtsPerWave + n;
+  const bool valid = p < a.n_points;
+  int64_t ray = 0;
+  int i = 0;
+  RayRec rr{};
+  if (a.mode == kModeRays && wave_id * kPtsPerWave < a.n_points) {
+    ray = (wave_id * kPtsPerWave) / a.N;
+    i = (int)(p - ray * a.N);
+    rr = a.rays[ray];
+  }
+  float x[3];
+  point_position(a, p, valid, ray, i, rr, x);
+
+  float e[RC];
+  encode_half<L>(a.lt, reinterpret_cast<const float2*>(a.table), x, h, e);
+  if (a.enc_out && wave_id * kPtsPerWave < a.n_points) {
+#pragma unroll
+    for (int r = 0; r < RC; ++r) a.enc_out[(wave_id * RC + r) * kWave + lane] = e[r];
+  }
+  float xh[RC], z[RC], rstd;
+  ln_forward<C>(e, sp + Ly::s_lng, sp + Ly::s_lnb, a.ln_eps, a.layernorm, h, xh, z, rstd);
+
+  float hb[D][RW];
+  layer_fwd<C, W>(sp + Ly::sW(0), sp + Ly::sb(0), z, hb[0], lane);
+#pragma unroll
+  for (int k = 1; k < D; ++k) layer_fwd<W, W>(sp + Ly::sW(k), sp + Ly::sb(k), hb[k - 1], hb[k], lane);
+  float yp = 0.0f;
+#pragma unroll
+  for (int R = 0; R < RW; ++R) yp += sp[Ly::s_wo + chan(R, h)] * hb[D - 1][R];
+  const float y = yp + xor32(yp) + sp[Ly::s_bo];
+  const float mu = act_fwd(a.out_act, a.mu_max, y);
+
+  if (a.mode == kModeRays) {
+    float c = (h == 0 && valid) ? mu * rr.delta : 0.0f;
+    c = half_sum(c);
+    if (lane == 0 && wave_id * kPtsPerWave < a.n_points) a.wave_sum[wave_id] = c;
+  } else if (h == 0 && valid) {
+    a.mu_out[p] = mu;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Backward kernel (persistent over 128-point chunks)
+// ---------------------------------------------------------------------------------------------
+template <int L, int W, int D>
+__global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b) {
+  constexpr int C = 2 * L, RC = C / 2, RW = W / 2;
+  using Ly = Lay<C, W, D>;
+  extern __shared__ float smem[];
+  float* sp = smem;
+  float* acc = smem + Ly::s_n;
+  const int nd_pad = (Ly::g_n + 3) & ~3;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
+  float* tG = acc + nd_pad + wv * (2 * 32 * kTile);
+  float* tH = tG + 32 * kTile;
+
+  stage_params<C, W, D>(a.dense, sp);
+  for (int e2 = threadIdx.x; e2 < nd_pad; e2 += blockDim.x) acc[e2] = 0.0f;
+  __syncthreads();
+
+  const int waves_per_ray = a.N / kPtsPerWave;
+  const int64_t n_chunks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
+  for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+    const int64_t wave_id = chunk * kWavesPerBlock + wv;
+    const int64_t p = wave_id * kPtsPerWave + n;
+    const bool wave_valid = wave_id * kPtsPerWave < a.n_points;
+    const bool valid = p < a.n_points;
+    int64_t ray = 0;
+    int i = 0;
+    RayRec rr{};
+    if (wave_valid) {
+      ray = (wave_id * kPtsPerWave) / a.N;
+      i = (int)(p - ray * a.N);
+      rr = a.rays[ray];
+    }
+    float x[3];
+    point_position(a, p, valid, ray, i, rr, x);
+
+    float e[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) e[r] = wave_valid ? b.enc_in[(wave_id * RC + r) * kWave + lane] : 0.0f;
+    float xh[RC], z[RC], rstd;
+    ln_forward<C>(e, sp + Ly::s_lng, sp + Ly::s_lnb, a.ln_eps, a.layernorm, h, xh, z, rstd);
+
+    float hb[D][RW];
+    layer_fwd<C, W>(sp + Ly::sW(0), sp + Ly::sb(0), z, hb[0], lane);
+#pragma unroll
+    for (int k = 1; k < D; ++k) layer_fwd<W, W>(sp + Ly::sW(k), sp + Ly::sb(k), hb[k - 1], hb[k], lane);
+    float yp = 0.0f;
+#pragma unroll
+    for (int R = 0; R < RW; ++R) yp += sp[Ly::s_wo + chan(R, h)] * hb[D - 1][R];
+    const float y = yp + xor32(yp) + sp[Ly::s_bo];
+
+    // Upstream gradient of the ray sum.
+    float dA = 0.0f;
+    if (wave_valid) {
+      if (b.dA_in) {
+        dA = b.dA_in[ray];
+      } else {
+        float A = 0.0f;
+        for (int w2 = 0; w2 < waves_per_ray; ++w2) A += a.wave_sum[ray * waves_per_ray + w2];
+        const float res = A - rr.a_gt;
+        dA = (float)((res > 0.0f) - (res < 0.0f)) * b.inv_R;
+        if (i == 0 && lane == 0) {
+          if (b.a_pred_out) b.a_pred_out[ray] = A;
+          if (b.absres_out) b.absres_out[ray] = fabsf(res);
+        }
+      }
+    }
+    const float dmu = (valid && rr.hit) ? dA * rr.delta : 0.0f;
+    const float dy = dmu * act_grad(a.out_act, a.mu_max, y);
+
+    // Output unit.
+    float g[RW];
+    float t[RW];
+#pragma unroll
+    for (int R = 0; R < RW; ++R) {
+      g[R] = dy * sp[Ly::s_wo + chan(R, h)];
+      t[R] = dy * hb[D - 1][R];
+    }
+#pragma unroll
+    for (int mb = 0; mb < W / 32; ++mb) {
+      tile_put<RW>(tG, t, mb, lane);
+      wave_lds_sync();
+      tile_rowsum_add(tG, acc, Ly::g_wo + 32 * mb, 32, lane);
+      wave_lds_sync();
+    }
+    {
+      const float sdy = half_sum(h == 0 ? dy : 0.0f);
+      if (lane == 0) atomicAdd(acc + Ly::g_bo, sdy);
+    }
+
+    // Hidden layers, last to first.
+    float gz[RC];
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k) {
+      float ga[RW];
+#pragma unroll
+      for (int R = 0; R < RW; ++R) ga[R] = hb[k][R] > 0.0f ? g[R] : 0.0f;
+      const int Kk = Ly::K(k);
+      const float* hin = (k == 0) ? z : hb[k > 0 ? k - 1 : 0];
+#pragma unroll
+      for (int mb = 0; mb < W / 32; ++mb) {
+        tile_put<RW>(tG, ga, mb, lane);
+        for (int nb = 0; nb < (Kk + 31) / 32; ++nb) {
+          if (k == 0) tile_put<RC>(tH, z, nb, lane);
+          else tile_put<RW>(tH, hin, nb, lane);
+          wave_lds_sync();
+          tile_outer_add(tG, tH, acc, Ly::gW(k), Kk, mb, nb, lane);
+          wave_lds_sync();
+        }
+        tile_rowsum_add(tG, acc, Ly::gb(k) + 32 * mb, 32, lane);
+        wave_lds_sync();
+      }
+      if (k > 0) {
+        float gp[RW];
+        layer_bwd_data<W, W>(sp + Ly::sW(k), ga, gp, lane);
+#pragma unroll
+        for (int R = 0; R < RW; ++R) g[R] = gp[R];
+      } else {
+        layer_bwd_data<C, W>(sp + Ly::sW(0), ga, gz, lane);
+      }
+    }
+
+    // LayerNorm backward.
+    float gx[RC];
+    if (a.layernorm) {
+      float t1[RC], t2[RC];
+      float sg = 0.0f, sgx = 0.0f;
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+        t1[r] = gz[r] * xh[r];
+        t2[r] = gz[r];
+        const float gg = sp[Ly::s_lng + chan(r, h)] * gz[r];
+        sg += gg;
+        sgx += gg * xh[r];
+      }
+      tile_put<RC>(tG, t1, 0, lane);
+      tile_put<RC>(tH, t2, 0, lane);
+      wave_lds_sync();
+      tile_rowsum_add(tG, acc, Ly::g_lng, C, lane);
+      tile_rowsum_add(tH, acc, Ly::g_lnb, C, lane);
+      wave_lds_sync();
+      sg += xor32(sg);
+      sgx += xor32(sgx);
+      const float mg = sg * (1.0f / C), mgx = sgx * (1.0f / C);
+#pragma unroll
+      for (int r = 0; r < RC; ++r)
+        gx[r] = rstd * (sp[Ly::s_lng + chan(r, h)] * gz[r] - mg - xh[r] * mgx);
+    } else {
+#pragma unroll
+      for (int r = 0; r < RC; ++r) gx[r] = gz[r];
+    }
+
+    if (valid && dmu != 0.0f) scatter_half<L>(a.lt, b.grad_table, x, h, gx);
+  }
+
+  __syncthreads();
+  for (int e2 = threadIdx.x; e2 < nd_pad; e2 += blockDim.x)
+    b.partials[(size_t)blockIdx.x * nd_pad + e2] = acc[e2];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------------------------
+__global__ void k_rays(const RaysArgs a) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n_rays) return;
+  const int32_t pix = a.pix_in ? a.pix_in[r] : draw_pixel(a.seed, a.step, a.h_bits, a.n_pix, (uint32_t)r);
+  RayRec rec;
+  const bool in_range = pix >= 0 && (uint32_t)pix < a.n_pix;
+  ray_setup(a.geo, a.ca, a.sa, in_range ? pix : 0, a.N, rec);
+  if (!in_range) {            // a pixel index outside the detector is a ray that misses
+    rec.hit = 0;
+    rec.delta = 0.0f;
+    rec.pix = pix;
+  }
+  rec.a_gt = (a.proj && in_range) ? a.proj[(size_t)a.view * a.n_pix + pix] : 0.0f;
+  a.rays[r] = rec;
+  if (a.pix_out) a.pix_out[r] = pix;
+  if (a.jitter_out)
+    for (int i = 0; i < a.N; ++i) a.jitter_out[(size_t)r * a.N + i] = jitter(a.seed, a.step, (uint32_t)r, (uint32_t)i);
+}
+
+// A_pred of each ray from the per-wave partial sums (fixed order).
+__global__ void k_raysum(const float* __restrict__ wave_sum, int waves_per_ray, int n_rays,
+                         float* __restrict__ a_pred) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rays) return;
+  float A = 0.0f;
+  for (int w = 0; w < waves_per_ray; ++w) A += wave_sum[(size_t)r * waves_per_ray + w];
+  a_pred[r] = A;
+}
+
+// grad_dense[k] += sum_g partials[g][k]; block 0 also forms loss = sum_r absres[r] * inv_R.
+__global__ void k_reduce(const float* __restrict__ partials, int n_blocks, int nd_pad, int nd,
+                         float* __restrict__ grad_dense, const float* __restrict__ absres, int n_rays,
+                         float inv_R, float* __restrict__ loss_out) {
+  __shared__ float red[256];
+  const int k = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int grp = threadIdx.x >> 6;
+  float s = 0.0f;
+  if (k < nd)
+    for (int gi = grp; gi < n_blocks; gi += 4) s += partials[(size_t)gi * nd_pad + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (grp == 0 && k < nd) grad_dense[k] += red[threadIdx.x] + red[threadIdx.x + 64] + red[threadIdx.x + 128] + red[threadIdx.x + 192];
+  if (blockIdx.x == 0 && loss_out) {
+    __syncthreads();
+    float l = 0.0f;
+    for (int r = threadIdx.x; r < n_rays; r += blockDim.x) l += absres[r];
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss_out = red[0] * inv_R;
+  }
+}
+
+// Adam (Kingma and Ba, Algorithm 1) over float4 groups; resets the gradient; refreshes the FP16
+// table copy when present.  n4 = number of float4 groups; the table occupies the first n_table
+// floats.
+__global__ void k_adam(float4* __restrict__ p, float4* __restrict__ g, float4* __restrict__ m,
+                       float4* __restrict__ v, int64_t n4, float lr, float b1, float b2, float eps,
+                       float ibc1, float ibc2, __half* __restrict__ th, int64_t n_table) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += stride) {
+    float4 pp = p[q], gg = g[q], mm = m[q], vv = v[q];
+    float* P = &pp.x;
+    float* G = &gg.x;
+    float* M = &mm.x;
+    float* V = &vv.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      M[k] = b1 * M[k] + (1.0f - b1) * G[k];
+      V[k] = b2 * V[k] + (1.0f - b2) * G[k] * G[k];
+      const float mh = M[k] * ibc1, vh = V[k] * ibc2;
+      P[k] -= lr * mh / (sqrtf(vh) + eps);
+    }
+    p[q] = pp;
+    m[q] = mm;
+    v[q] = vv;
+    g[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (th && 4 * q < n_table) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (4 * q + k < n_table) th[4 * q + k] = __float2half_rn(P[k]);
+    }
+  }
+}
+
+__global__ void k_fill(float* __restrict__ x, int64_t n, float val) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) x[q] = val;
+}
+
+__global__ void k_to_half(const float* __restrict__ src, __half* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) dst[q] = __float2half_rn(src[q]);
+}
+
+// Initial values: table (2u - 1) 1e-4; linear layer weights and biases (2u - 1) / sqrt(fan_in);
+// LayerNorm gain 1, bias 0.  u from Philox with counter (index, 0/hi, 0, stream).
+__global__ void k_init(float* __restrict__ params, int64_t n_table, int64_t dense_off, InitArgs ia) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_table; q += stride) {
+    const float u = u24f(philox_w0(ia.seed, (uint32_t)q, (uint32_t)((uint64_t)q >> 32), 0, kTable));
+    params[q] = (2.0f * u - 1.0f) * 1e-4f;
+  }
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ia.n_dense; k += stride) {
+    float val;
+    if (k < ia.ln_end) {
+      val = (k < ia.ln_end / 2) ? 1.0f : 0.0f;
+    } else {
+      int fan = ia.width;
+      if (k < ia.first_layer_end) fan = ia.fan0;
+      const float u = u24f(philox_w0(ia.seed, (uint32_t)k, 0, 0, kMlp));
+      val = (2.0f * u - 1.0f) / sqrtf((float)fan);
+    }
+    params[dense_off + k] = val;
+  }
+}
+
+// Raw encoding of n points (all levels, natural channel order) and optional corner entries.
+__global__ void k_encode(const LevelTab lt, const float2* __restrict__ table, const float* __restrict__ xn,
+                         int64_t n, float* __restrict__ enc, uint32_t* __restrict__ idx_out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n * lt.L) return;
+  const int64_t p = q / lt.L;
+  const int l = (int)(q - p * lt.L);
+  const float x[3] = {xn[3 * p], xn[3 * p + 1], xn[3 * p + 2]};
+  uint32_t idx[8];
+  float w[8];
+  level_corners(lt.res[l], lt.off[l], lt.stride[l], lt.mask, x, idx, w);
+  float s0 = 0.0f, s1 = 0.0f;
+  for (int c = 0; c < 8; ++c) {
+    const float2 v = table[idx[c]];
+    s0 += w[c] * v.x;
+    s1 += w[c] * v.y;
+  }
+  enc[p * 2 * lt.L + 2 * l] = s0;
+  enc[p * 2 * lt.L + 2 * l + 1] = s1;
+  if (idx_out)
+    for (int c = 0; c < 8; ++c) idx_out[(p * lt.L + l) * 8 + c] = idx[c];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------------------------
+template <int L, int W, int D>
+static KernelSet make_set() {
+  constexpr int C = 2 * L;
+  using Ly = Lay<C, W, D>;
+  KernelSet ks;
+  ks.fwd = reinterpret_cast<const void*>(&k_fwd<L, W, D>);
+  ks.bwd = reinterpret_cast<const void*>(&k_bwd<L, W, D>);
+  ks.fwd_lds = Ly::s_n * sizeof(float);
+  const int nd_pad = (Ly::g_n + 3) & ~3;
+  ks.bwd_lds = (Ly::s_n + nd_pad + kWavesPerBlock * 2 * 32 * kTile) * sizeof(float);
+  ks.n_dense = Ly::g_n;
+  ks.nd_pad = nd_pad;
+  ks.valid = true;
+  return ks;
+}
+
+KernelSet kernel_set(int L, int W, int D, int precision) {
+  if (precision != 0) return KernelSet{};
+#define NIC_CASE(l, w, d) \
+  if (L == l && W == w && D == d) return make_set<l, w, d>();
+  NIC_CASE(8, 32, 1) NIC_CASE(8, 32, 2) NIC_CASE(8, 32, 3) NIC_CASE(8, 32, 4)
+  NIC_CASE(16, 32, 1) NIC_CASE(16, 32, 2) NIC_CASE(16, 32, 3) NIC_CASE(16, 32, 4)
+  NIC_CASE(8, 64, 4) NIC_CASE(16, 64, 4)
+#undef NIC_CASE
+  return KernelSet{};
+}
+
+hipError_t launch_fwd(const KernelSet& ks, const FwdArgs& a, hipStream_t s) {
+  const int64_t blocks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
+  if (blocks == 0) return hipSuccess;
+  void* args[] = {const_cast<FwdArgs*>(&a)};
+  return hipLaunchKernel(ks.fwd, dim3((unsigned)blocks), dim3(kBlock), args, ks.fwd_lds, s);
+}
+
+hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, int grid, hipStream_t s) {
+  void* args[] = {const_cast<FwdArgs*>(&a), const_cast<BwdArgs*>(&b)};
+  return hipLaunchKernel(ks.bwd, dim3((unsigned)grid), dim3(kBlock), args, ks.bwd_lds, s);
+}
+
+hipError_t launch_rays(const RaysArgs& a, hipStream_t s) {
+  if (a.n_rays == 0) return hipSuccess;
+  k_rays<<<(a.n_rays + 127) / 128, 128, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_raysum(const float* ws, int wpr, int n_rays, float* out, hipStream_t s) {
+  if (n_rays == 0) return hipSuccess;
+  k_raysum<<<(n_rays + 255) / 256, 256, 0, s>>>(ws, wpr, n_rays, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const float* partials, int n_blocks, int nd_pad, int nd, float* grad_dense,
+                         const float* absres, int n_rays, float inv_R, float* loss_out, hipStream_t s) {
+  k_reduce<<<(nd + 63) / 64, 256, 0, s>>>(partials, n_blocks, nd_pad, nd, grad_dense, absres, n_rays, inv_R,
+                                         loss_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, float ibc1, float ibc2, __half* th, int64_t n_table, int n_cu, hipStream_t s) {
+  const int64_t n4 = n / 4;
+  int64_t blocks = (n4 + 255) / 256;
+  const int64_t cap = (int64_t)n_cu * 16;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  k_adam<<<(unsigned)blocks, 256, 0, s>>>(reinterpret_cast<float4*>(p), reinterpret_cast<float4*>(g),
+                                          reinterpret_cast<float4*>(m), reinterpret_cast<float4*>(v), n4, lr, b1,
+                                          b2, eps, ibc1, ibc2, th, n_table);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* x, int64_t n, float val, int n_cu, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > (int64_t)n_cu * 16) blocks = (int64_t)n_cu * 16;
+  k_fill<<<(unsigned)blocks, 256, 0, s>>>(x, n, val);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_half(const float* src, __half* dst, int64_t n, int n_cu, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > (int64_t)n_cu * 16) blocks = (int64_t)n_cu * 16;
+  k_to_half<<<(unsigned)blocks, 256, 0, s>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const InitArgs& ia, int n_cu,
+                       hipStream_t s) {
+  int64_t blocks = (n_table + 255) / 256;
+  if (blocks > (int64_t)n_cu * 16) blocks = (int64_t)n_cu * 16;
+  if (blocks < 1) blocks = 1;
+  k_init<<<(unsigned)blocks, 256, 0, s>>>(params, n_table, dense_off, ia);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(const LevelTab& lt, const float* table, const float* xn, int64_t n, float* enc,
+                         uint32_t* idx, hipStream_t s) {
+  const int64_t tot = n * lt.L;
+  if (tot == 0) return hipSuccess;
+  k_encode<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(lt, reinterpret_cast<const float2*>(table), xn, n, enc,
+                                                         idx);
+  return hipGetLastError();
+}
+
+}  // namespace nic

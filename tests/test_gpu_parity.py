@@ -1,0 +1,335 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs.
+
+Bars: corner entries bit-exact; forward values (encoding, mu, ray sums, loss) within 1e-5 and
+gradients / post-Adam parameters within 1e-4, both as max|gpu - oracle| / max|oracle| per tensor
+(entries near zero make an elementwise relative error meaningless).  Random draws (pixels, jitter)
+are either given to both sides as data or drawn by both from Philox and compared bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2506_19742_amd import nic, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+def rel(gpu, ora):
+    gpu = np.asarray(gpu, np.float64)
+    ora = np.asarray(ora, np.float64)
+    scale = np.abs(ora).max()
+    return float(np.abs(gpu - ora).max() / (scale if scale > 0 else 1.0))
+
+
+def ocfg(ora, cfg: nic.Config):
+    return ora.Config(n_levels=cfg.n_levels, feats=cfg.feats_per_level, log2_table=cfg.log2_table,
+                      base_res=cfg.base_res, max_res=cfg.max_res, depth=cfg.mlp_depth,
+                      width=cfg.mlp_width, out_act=cfg.out_act, layernorm=cfg.layernorm,
+                      mu_max=cfg.mu_max, ln_eps=cfg.ln_eps)
+
+
+def random_params(ora, oc, seed, table_scale):
+    """Flat [table | dense] parameters: table N(0, table_scale), LN gain near 1, MLP uniform."""
+    tot, nt, nd = ora.n_params(oc)
+    lay = ora.dense_layout(oc)
+    rng = np.random.default_rng(seed)
+    p = synth.init_params(nt // 2, 2, lay, oc.depth, seed).astype(np.float64)
+    p[:nt] = rng.standard_normal(nt) * table_scale
+    o, n = lay["ln_g"]
+    p[nt + o:nt + o + n] = 1.0 + 0.1 * rng.standard_normal(n)
+    o, n = lay["ln_b"]
+    p[nt + o:nt + o + n] = 0.05 * rng.standard_normal(n)
+    return p.astype(np.float32).astype(np.float64)
+
+
+class Case:
+    """A model on the GPU plus the same scan on the host."""
+
+    def __init__(self, ora, wname, seed=11, **over):
+        w = synth.WORKLOADS[wname]
+        self.w = w
+        self.cfg = nic.config_for(w, seed=seed, **over)
+        self.ph, self.g, self.A = synth.scan(w)
+        self.oc = ocfg(ora, self.cfg)
+        print(f"[case] {wname} {over} creating model", flush=True)
+        self.model = nic.Model(self.cfg, self.g)
+        self.proj = torch.tensor(self.A, device="cuda")
+        self.model.set_projections(self.proj)
+
+    def set_params(self, p):
+        self.model.load_params(p)
+
+    def params(self):
+        return self.model.flat(self.model.tensors()[0])
+
+    def grads(self):
+        return self.model.flat(self.model.tensors()[1])
+
+
+@pytest.fixture(scope="module")
+def tiny(ora):
+    return Case(ora, "tiny64")
+
+
+def _pts(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.random((n, 3)).astype(np.float32)
+    # faces, edges and corners of the unit cube and exact grid vertices of a power-of-two level
+    x[:8] = np.array([[0, 0, 0], [1, 1, 1], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0], [0.5, 1, 0.25],
+                      [0.0, 0.5, 1.0]], np.float32)
+    x[8:40] = (rng.integers(0, 17, (32, 3)) / 16).astype(np.float32)
+    return x
+
+
+def test_encode_indices_bit_exact_and_values(ora, tiny):
+    c = tiny
+    p = random_params(ora, c.oc, 1, 0.1)
+    c.set_params(p)
+    x = _pts(5000, 2)
+    print("[gpu] nic_encode 5000 points", flush=True)
+    enc, idx = c.model.encode(torch.tensor(x, device="cuda"), want_idx=True)
+    oenc, oidx, _ = ora.encode(c.oc, p[:ora.n_params(c.oc)[1]], x, want_idx=True)
+    assert np.array_equal(idx.cpu().numpy().astype(np.uint32), oidx)
+    assert rel(enc.cpu().numpy(), oenc) <= FWD_TOL
+
+
+def test_encode_all_collision_table(ora):
+    """T = 32 entries per hashed level: every hashed level collides heavily."""
+    c = Case(ora, "tiny64", log2_table=5, base_res=2, max_res=64)
+    lay = c.model.layout
+    assert sum(lay["dense"]) >= 1 and not all(lay["dense"])
+    p = random_params(ora, c.oc, 3, 0.1)
+    c.set_params(p)
+    x = _pts(3000, 4)
+    enc, idx = c.model.encode(torch.tensor(x, device="cuda"), want_idx=True)
+    oenc, oidx, _ = ora.encode(c.oc, p[:ora.n_params(c.oc)[1]], x, want_idx=True)
+    assert np.array_equal(idx.cpu().numpy().astype(np.uint32), oidx)
+    assert rel(enc.cpu().numpy(), oenc) <= FWD_TOL
+    c.model.close()
+
+
+@pytest.mark.parametrize("scale", [1e-4, 0.1])
+def test_query_matches_oracle(ora, tiny, scale):
+    c = tiny
+    p = random_params(ora, c.oc, 5, scale)
+    c.set_params(p)
+    x = _pts(3001, 6)                       # not a multiple of the 32-point wave tile
+    mu = c.model.query(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert rel(mu, ora.field(c.oc, p, x)) <= FWD_TOL
+
+
+def test_render_volume_matches_oracle(ora, tiny):
+    c = tiny
+    p = random_params(ora, c.oc, 7, 0.1)
+    c.set_params(p)
+    vol = c.model.render_volume(9, 7, 5).cpu().numpy()
+    assert rel(vol, ora.render_volume(c.oc, p, 9, 7, 5)) <= FWD_TOL
+
+
+def _rays(c, R, seed):
+    pix, jit = synth.ray_batch(seed, c.g.n_pix, R, c.cfg.samples_per_ray)
+    return pix, jit, torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda")
+
+
+@pytest.mark.parametrize("R", [1, 37, 1024])
+def test_forward_ray_sums_match_oracle(ora, tiny, R):
+    c = tiny
+    p = random_params(ora, c.oc, 9, 0.1)
+    c.set_params(p)
+    pix, jit, tp, tj = _rays(c, R, 10 + R)
+    v = 17
+    a = c.model.forward(v, tp, tj).cpu().numpy()
+    _, oa, _ = ora.ray_batch(c.oc, c.g, p, float(c.g.angles[v]), c.A[v], pix, jit, grad=False)
+    assert rel(a, oa) <= FWD_TOL
+
+
+def test_backward_gradients_match_oracle(ora, tiny):
+    c = tiny
+    p = random_params(ora, c.oc, 12, 0.1)
+    c.set_params(p)
+    pix, jit, tp, tj = _rays(c, 256, 13)
+    v = 3
+    dA = np.random.default_rng(14).standard_normal(256).astype(np.float32)
+    c.model.zero_grad()
+    c.model.backward(v, tp, tj, torch.tensor(dA, device="cuda"))
+    g = c.grads()
+    _, _, og = ora.ray_batch(c.oc, c.g, p, float(c.g.angles[v]), c.A[v], pix, jit, dA=dA)
+    nt = ora.n_params(c.oc)[1]
+    assert rel(g[:nt], og[:nt]) <= GRAD_TOL
+    assert rel(g[nt:], og[nt:]) <= GRAD_TOL
+    lay = ora.dense_layout(c.oc)
+    for name, on in lay.items():
+        if name == "n":
+            continue
+        o, n = on
+        assert rel(g[nt + o:nt + o + n], og[nt + o:nt + o + n]) <= GRAD_TOL, name
+
+
+def test_backward_accumulates(ora, tiny):
+    """Two backward calls without zeroing add up."""
+    c = tiny
+    p = random_params(ora, c.oc, 15, 0.1)
+    c.set_params(p)
+    pix, jit, tp, tj = _rays(c, 64, 16)
+    dA = torch.full((64,), 0.5, device="cuda")
+    c.model.zero_grad()
+    c.model.backward(1, tp, tj, dA)
+    g1 = c.grads()
+    c.model.backward(1, tp, tj, dA)
+    g2 = c.grads()
+    assert rel(g2, 2 * g1) <= 1e-6
+
+
+def test_adam_matches_oracle(ora, tiny):
+    c = tiny
+    p = random_params(ora, c.oc, 17, 0.1)
+    c.set_params(p)
+    P, G, M, V, _ = c.model.tensors()
+    M.zero_()
+    V.zero_()
+    nt, nd, do = c.model.n_params()
+    rng = np.random.default_rng(18)
+    om, ov, op = np.zeros_like(p), np.zeros_like(p), p.copy()
+    step0 = c.model.get_step()
+    for t in range(1, 4):
+        g = (rng.standard_normal(len(p)) * 1e-2).astype(np.float32).astype(np.float64)
+        g[::5] = 0.0
+        G.zero_()
+        G[:nt].copy_(torch.tensor(g[:nt], dtype=torch.float32))
+        G[do:do + nd].copy_(torch.tensor(g[nt:], dtype=torch.float32))
+        c.model.adam()
+        ora.adam(op, g, om, ov, step0 + t)
+    assert rel(c.params(), op) <= GRAD_TOL
+    assert float(G.abs().max()) == 0.0
+
+
+def test_l1_step_matches_oracle(ora, tiny):
+    """Full training steps (Eq. 3 loss, backward, Adam) with explicit rays and jitter."""
+    c = tiny
+    p = random_params(ora, c.oc, 19, 1e-4)
+    c.set_params(p)
+    c.model.zero_grad()
+    c.model.tensors()[2].zero_()
+    c.model.tensors()[3].zero_()
+    t0 = c.model.get_step()
+    op, om, ov = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    loss = torch.zeros(1, device="cuda")
+    for k in range(3):
+        pix, jit, tp, tj = _rays(c, 1024, 20 + k)
+        v = (5 * k + 2) % 50
+        c.model.step(v, tp, tj, loss)
+        ol, _, og = ora.ray_batch(c.oc, c.g, op, float(c.g.angles[v]), c.A[v], pix, jit)
+        ora.adam(op, og, om, ov, t0 + k + 1)
+        assert abs(loss.item() - ol) <= FWD_TOL * abs(ol)
+    assert rel(c.params(), op) <= GRAD_TOL
+
+
+def test_device_draws_match_oracle(ora, tiny):
+    """Pixels (Feistel over Philox, cycle walking) and jitter drawn on the GPU, bit for bit."""
+    c = tiny
+    for step in [0, 1, 777]:
+        pix, jit = c.model.draw_rays(step)
+        opix, ojit = ora.draw_rays(c.cfg.seed, step, c.g.n_pix, c.cfg.rays_per_step, c.cfg.samples_per_ray)
+        assert np.array_equal(pix.cpu().numpy(), opix)
+        assert np.array_equal(jit.cpu().numpy(), ojit)
+    for step in range(0, 120, 7):
+        assert c.model.view_for_step(step) == ora.view_for_step(c.cfg.seed, step, 50)
+
+
+def test_device_init_matches_oracle(ora, tiny):
+    c = tiny
+    c.model.init_params(1234)
+    p = c.params()
+    op = ora.init_params(c.oc, 1234)
+    assert rel(p, op) <= 1e-6
+
+
+def test_train_with_device_draws_matches_oracle(ora, tiny):
+    """nic_train (every draw on the device) against the oracle's own Philox schedule."""
+    c = tiny
+    c.model.init_params(c.cfg.seed)
+    p = c.params()
+    losses = c.model.train(4)
+    op, om, ov = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    ol = ora.train(c.oc, c.g, c.g.angles, c.A, op, om, ov, 0, 4, c.cfg.rays_per_step,
+                   c.cfg.samples_per_ray, c.cfg.seed)
+    assert rel(losses, ol) <= FWD_TOL
+    assert rel(c.params(), op) <= GRAD_TOL
+
+
+def test_rays_missing_the_box(ora):
+    """A detector shifted far sideways: some rays miss the box (A = 0, no gradient)."""
+    w = synth.WORKLOADS["tiny64"]
+    cfg = nic.config_for(w, rays_per_step=256)
+    g = synth.cone_geometry(64, 8)
+    g.off_u = 150.0
+    oc = ocfg(ora, cfg)
+    m = nic.Model(cfg, g)
+    p = random_params(ora, oc, 21, 0.1)
+    m.load_params(p)
+    pix, jit = synth.ray_batch(22, g.n_pix, 256, 64)
+    a = m.forward(0, torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda")).cpu().numpy()
+    proj = np.zeros(g.n_pix, np.float32)
+    _, oa, _ = ora.ray_batch(oc, g, p, float(g.angles[0]), proj, pix, jit, grad=False)
+    assert (oa == 0).sum() > 10 and (oa > 0).sum() > 10
+    assert np.all(a[oa == 0] == 0)
+    assert rel(a, oa) <= FWD_TOL
+    m.close()
+
+
+@pytest.mark.parametrize("N,depth", [(32, 1), (320, 2)])
+def test_other_shapes_forward_backward(ora, N, depth):
+    w = synth.WORKLOADS["tiny64"]
+    cfg = nic.config_for(w, samples_per_ray=N, mlp_depth=depth, rays_per_step=96)
+    g = synth.cone_geometry(64, 50)
+    ph = synth.make_phantom(1, 6)
+    A = synth.project(ph, g).astype(np.float32)
+    oc = ocfg(ora, cfg)
+    m = nic.Model(cfg, g)
+    m.set_projections(torch.tensor(A, device="cuda"))
+    p = random_params(ora, oc, 23, 0.1)
+    m.load_params(p)
+    pix, jit = synth.ray_batch(24, g.n_pix, 96, N)
+    tp, tj = torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda")
+    a = m.forward(9, tp, tj).cpu().numpy()
+    dA = np.random.default_rng(25).standard_normal(96).astype(np.float32)
+    m.zero_grad()
+    m.backward(9, tp, tj, torch.tensor(dA, device="cuda"))
+    gr = m.flat(m.tensors()[1])
+    _, oa, og = ora.ray_batch(oc, g, p, float(g.angles[9]), A[9], pix, jit, dA=dA)
+    assert rel(a, oa) <= FWD_TOL
+    nt = ora.n_params(oc)[1]
+    assert rel(gr[:nt], og[:nt]) <= GRAD_TOL
+    assert rel(gr[nt:], og[nt:]) <= GRAD_TOL
+    m.close()
+
+
+def test_paper_scale_sampled_rays(ora):
+    """256^3 workload (16 levels, T = 2^19, 4x32 MLP, 192 samples): the full 2048-ray forward in the
+    launch configuration of the benchmark, checked on a sample of rays computed by the oracle."""
+    c = Case(ora, "ct256")
+    p = random_params(ora, c.oc, 26, 0.05)
+    c.set_params(p)
+    pix, jit, tp, tj = _rays(c, 2048, 27)
+    v = 11
+    a = c.model.forward(v, tp, tj).cpu().numpy()
+    sel = np.random.default_rng(28).choice(2048, 24, replace=False)
+    _, oa, _ = ora.ray_batch(c.oc, c.g, p, float(c.g.angles[v]), c.A[v], pix[sel], jit[sel], grad=False)
+    assert rel(a[sel], oa) <= FWD_TOL
+    # gradient of the sampled rays alone (dA zero elsewhere) against the oracle
+    dA = np.zeros(2048, np.float32)
+    dA[sel] = np.random.default_rng(29).standard_normal(24).astype(np.float32)
+    c.model.zero_grad()
+    c.model.backward(v, tp, tj, torch.tensor(dA, device="cuda"))
+    g = c.grads()
+    _, _, og = ora.ray_batch(c.oc, c.g, p, float(c.g.angles[v]), c.A[v], pix[sel], jit[sel], dA=dA[sel])
+    nt = ora.n_params(c.oc)[1]
+    assert rel(g[:nt], og[:nt]) <= GRAD_TOL
+    assert rel(g[nt:], og[nt:]) <= GRAD_TOL
+    c.model.close()
