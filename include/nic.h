@@ -74,6 +74,10 @@ typedef struct nic_config {
   int32_t layernorm;          /* 1: LayerNorm between encoder and network (Sec. 2.3), 0: none */
   int32_t precision;          /* 0: FP32; 1: BF16 MLP operands (FP32 accumulate) + FP16 table
                                  copy for gathers, FP32 master weights, grads and Adam */
+  int32_t n_tables;           /* K hash tables sharing one LayerNorm + MLP (pre-training for
+                                 Mapping Consistency Initialization, Sec. 2.4); 0 or 1 = one table.
+                                 Ray training and rendering use table 0. */
+  int32_t pad_;
   double mu_max;              /* output scale for out_act 0 (1/mm) */
   double ln_eps;              /* LayerNorm epsilon */
   double lr, beta1, beta2, adam_eps;   /* Adam (Sec. 3.1: lr 1e-3) */
@@ -86,8 +90,8 @@ typedef struct nic_layout {
   int32_t res[16];            /* N_l */
   int32_t dense[16];          /* 1 when the level stores one entry per vertex */
   int64_t offset[16];         /* first entry of the level */
-  int64_t n_entries;          /* table entries (each feats_per_level floats) */
-  int64_t n_table;            /* table parameters = n_entries * feats_per_level */
+  int64_t n_entries;          /* entries of one table (each feats_per_level floats) */
+  int64_t n_table;            /* table parameters = n_tables * n_entries * feats_per_level */
   int64_t n_dense;            /* LayerNorm + MLP parameters */
   int64_t dense_offset;       /* index of the first dense parameter in the parameter vector */
   int64_t n_params_padded;    /* length of the parameter vector (padding entries stay 0) */
@@ -104,7 +108,7 @@ typedef struct nic_tensor {
 } nic_tensor;
 
 /* Level table and parameter counts of a configuration.  Parameter vector layout:
- * [table: n_entries x F, entry-major, level after level][padding][dense block][padding], dense
+ * [tables: n_tables x n_entries x F, entry-major, level after level][padding][dense block][padding], dense
  * block = ln_gain[C] ln_bias[C] then per hidden layer k: W_k[W][in_k] (row = output unit) b_k[W],
  * then w_out[W] b_out[1], with C = L*F, in_0 = C, in_k = W.  Returns NIC_EINVAL for an
  * unsupported configuration.  Host only. */
@@ -185,18 +189,49 @@ nic_status nic_query(nic_model* m, const float* xn_dev, int64_t n, float* mu_dev
  * [nz][ny][nx]); dims = {nx, ny, nz}. */
 nic_status nic_render_volume(nic_model* m, const int32_t dims[3], float* vol_dev);
 
-/* Raw encoding (before LayerNorm) at n normalised points: enc_dev (device float32 [n][L*F], channel
+/* Raw encoding (before LayerNorm) at n normalised points, gathered from the table the forward pass
+ * uses (FP32, or the FP16 copy when precision == 1): enc_dev (device float32 [n][L*F], channel
  * l*F + f) and, when idx_dev != NULL, the global table entry of every corner (device uint32
  * [n][L][8], corner c = c0 + 2 c1 + 4 c2). */
 nic_status nic_encode(nic_model* m, const float* xn_dev, int64_t n, float* enc_dev, uint32_t* idx_dev);
+
+/* Voxel loss step for the pre-training of Mapping Consistency Initialization (Sec. 2.1 and
+ * Sec. 2.4, Eq. 2): n_points points of the unit cube, split into n_tables equal contiguous groups
+ * (point p uses table p / (n_points / n_tables)), target mu = trilinear sample of that table's volume
+ * (set by nic_set_volumes), loss = mean |mu - target|, then backward and Adam as in nic_step.
+ * xn_dev: device float32 [n_points][3] in [0, 1], or NULL to draw the points on the device
+ * (Philox, step counter as counter).  n_points must be a multiple of 32 * n_tables and at most
+ * rays_per_step * samples_per_ray.  loss_dev: device float32 [1] or NULL.  Increments the step. */
+nic_status nic_voxel_step(nic_model* m, const float* xn_dev, int32_t n_points, float* loss_dev);
+
+/* n_steps voxel steps with device-drawn points; loss_host as in nic_train. */
+nic_status nic_voxel_train(nic_model* m, int32_t n_steps, int32_t n_points, float* loss_host);
+
+/* Borrows the pre-training target volumes: device float32 [n_tables][n][n][n] (z, y, x order,
+ * voxel-centre sampling, n >= 2). */
+nic_status nic_set_volumes(nic_model* m, const float* vols_dev, int32_t n);
+
+/* Mapping Consistency Initialization transfer (Sec. 2.1, Sec. 3.1): only the LayerNorm and MLP
+ * weights move between models.  nic_export_mlp writes a host blob (header + FP32 dense block);
+ * with buf == NULL it only stores the size in *bytes.  nic_import_mlp loads a blob of a model with
+ * the same channel count, width, depth, output activation and LayerNorm flag into the dense block
+ * and resets its Adam moments (the hash table keeps its own values).  Both synchronise the stream;
+ * NIC_EVERSION for a blob of another format or shape. */
+nic_status nic_export_mlp(nic_model* m, void* buf, size_t* bytes);
+nic_status nic_import_mlp(nic_model* m, const void* buf, size_t bytes);
+
+/* PSNR = 10 log10(max(gt)^2 / mean((pred - gt)^2)) over n voxels (device float32 arrays); the
+ * squared errors are summed in FP64 on the device; synchronous.  +inf when pred == gt. */
+nic_status nic_psnr(nic_model* m, const float* gt_dev, const float* pred_dev, int64_t n, double* psnr_host);
 
 /* Current Adam step count (host only). */
 int64_t nic_get_step(const nic_model* m);
 
 /* Kernel timing for benchmarks: with enable != 0, every kernel of the training path is bracketed
  * by a pair of HIP events on the model's stream.  nic_kernel_times synchronises the stream and
- * returns, per kernel kind k (0 rays, 1 forward, 2 backward, 3 reduce, 4 adam), the total
- * milliseconds ms[k] and the number of launches calls[k] since timing was enabled (*count = 5). */
+ * returns, per kernel kind k (0 rays, 1 forward, 2 backward, 3 dense-gradient reduce, 4 adam,
+ * 5 bin scan, 6 bin reduce), the total milliseconds ms[k] and the number of launches calls[k]
+ * since timing was enabled; ms and calls must hold 8 entries (*count = 7). */
 nic_status nic_set_timing(nic_model* m, int32_t enable);
 nic_status nic_kernel_times(nic_model* m, double* ms, int64_t* calls, int32_t* count);
 

@@ -69,6 +69,7 @@ def lib():
         L.ora_view_for_step.restype = C.c_int32
         L.ora_draw_rays.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_int32, C.c_int32, i32, f]
         L.ora_init_params.argtypes = [P(Cfg), C.c_uint64, d]
+        L.ora_voxel_points.argtypes = [C.c_uint64, C.c_uint32, C.c_int32, f]
         L.ora_vertex_index.argtypes = [P(Cfg), C.c_int, C.c_uint32, C.c_uint32, C.c_uint32]
         L.ora_vertex_index.restype = C.c_uint32
         L.ora_encode.argtypes = [P(Cfg), d, f, C.c_int64, d, u32, d]
@@ -187,6 +188,12 @@ def draw_rays(seed: int, t: int, n_pix: int, R: int, N: int):
 
 def view_for_step(seed: int, t: int, V: int) -> int:
     return int(lib().ora_view_for_step(seed, t, V))
+
+
+def voxel_points(seed: int, t: int, n: int):
+    xn = np.zeros((n, 3), np.float32)
+    lib().ora_voxel_points(seed, t, n, _p(xn, C.c_float))
+    return xn
 
 
 def init_params(cfg: Config, seed: int):

@@ -234,6 +234,18 @@ void ora_draw_rays(uint64_t seed, uint32_t t, int64_t n_pix, int32_t R, int32_t 
   }
 }
 
+/* Points of a voxel-loss step (pre-training, Eq. 2): point p of step t takes its three normalised
+ * coordinates from the first three words of the Philox block (p, t, 0, stream). */
+void ora_voxel_points(uint64_t seed, uint32_t t, int32_t n, float* xn) {
+  for (int32_t p = 0; p < n; ++p) {
+    uint32_t ctr[4] = {(uint32_t)p, t, 0u, ORA_S_POINTS};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    ora_philox4x32_10(ctr, key, out);
+    for (int k = 0; k < 3; ++k) xn[3 * (int64_t)p + k] = (float)u24(out[k]);
+  }
+}
+
 /* Initial parameters: table entries uniform in [-1e-4, 1e-4); linear layers uniform in
  * [-1/sqrt(fan_in), 1/sqrt(fan_in)) (the usual default for linear layers; the paper states no
  * initialisation); LayerNorm gain 1 and bias 0. */

@@ -39,6 +39,18 @@ nic_status fail(nic_status st, const char* fmt, ...) {
 constexpr int64_t kAlign = 256;
 constexpr int kMaxBwdBlocks = 2048;
 constexpr int kLossHist = 4096;
+constexpr int kSqerrBlocks = 1024;
+
+// Blob of the LayerNorm + MLP weights (Mapping Consistency Initialization transfer): this header,
+// then the dense block in the parameter-vector order (FP32).
+struct MlpBlobHeader {
+  char magic[4];
+  uint32_t version;
+  int32_t channels, width, depth, out_act, layernorm, n_dense;
+  double mu_max, ln_eps;
+};
+constexpr uint32_t kBlobVersion = 1;
+constexpr int kKinds = 7;   // timed kernel kinds: rays, forward, backward, reduce, adam, bin scan, bin reduce
 
 int64_t up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -48,10 +60,16 @@ struct Plan {
   int32_t res[kMaxLevels]{}, dense[kMaxLevels]{};
   int64_t off[kMaxLevels]{};
   int64_t n_entries = 0, n_table = 0, n_dense = 0, nd_pad = 0, dense_off = 0, n_params_pad = 0;
+  int32_t n_tables = 1;
+  int64_t o_sqerr = 0;
   int C = 0;
   KernelSet ks;
   // workspace offsets (bytes)
   int64_t o_params, o_grads, o_m, o_v, o_th, o_part, o_rays, o_wsum, o_enc, o_apred, o_absres, o_loss, o_pix;
+  int64_t o_counts, o_offs, o_pieces, o_npieces, o_recs, o_totals, o_binstart;
+  uint32_t dense_end = 0;
+  int n_bins = 0;
+  int64_t max_pieces = 0;
   int64_t bytes = 0;
 };
 
@@ -74,6 +92,7 @@ std::string check_config(const nic_config* c) {
   if (!(c->lr > 0) || !std::isfinite(c->lr)) return "lr must be positive";
   if (!(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1)) return "betas must be in [0, 1)";
   if (!(c->adam_eps > 0) || !std::isfinite(c->adam_eps)) return "adam_eps must be positive";
+  if (c->n_tables < 0 || c->n_tables > 256) return "n_tables must be in [0, 256]";
   return "";
 }
 
@@ -120,9 +139,10 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
   }
   p.lt.mask = (uint32_t)(T - 1);
   p.lt.L = L;
+  p.n_tables = c->n_tables > 1 ? c->n_tables : 1;
   p.n_entries = off;
-  p.n_table = off * 2;
-  if (p.n_table >= (1ll << 31)) { err = "hash table too large"; return false; }
+  p.n_table = off * 2 * p.n_tables;
+  if (p.n_table >= (1ll << 31)) { err = "hash tables too large"; return false; }
   p.C = 2 * L;
   p.ks = kernel_set(L, c->mlp_width, c->mlp_depth, c->precision);
   if (!p.ks.valid) { err = "unsupported (levels, width, depth, precision) combination"; return false; }
@@ -147,6 +167,20 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
   p.o_absres = take(R * 4);
   p.o_loss = take(kLossHist * 4);
   p.o_pix = take(R * 4);
+  p.n_bins = (int)((p.n_entries * p.n_tables + (1 << kBinBits) - 1) >> kBinBits);
+  const int64_t max_recs = R * N * L * 8;
+  p.max_pieces = p.n_bins + max_recs / kPiece + 1;
+  p.dense_end = 0;
+  for (int l = 0; l < L; ++l)
+    if (p.dense[l]) p.dense_end = (uint32_t)(p.off[l] + ((int64_t)p.res[l] + 1) * (p.res[l] + 1) * (p.res[l] + 1));
+  p.o_totals = take((int64_t)p.n_bins * 4);
+  p.o_binstart = take((int64_t)p.n_bins * 4);
+  p.o_counts = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
+  p.o_offs = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
+  p.o_pieces = take(p.max_pieces * 16);
+  p.o_npieces = take(4);
+  p.o_recs = take(max_recs * (int64_t)sizeof(BinRec));
+  p.o_sqerr = take(2 * kSqerrBlocks * 8);
   p.bytes = o;
   return true;
 }
@@ -170,6 +204,14 @@ struct nic_model {
   float *partials = nullptr, *wsum = nullptr, *enc = nullptr, *apred = nullptr, *absres = nullptr, *loss = nullptr;
   RayRec* rays = nullptr;
   int32_t* pix = nullptr;
+  uint32_t *counts = nullptr, *offs = nullptr, *totals = nullptr, *bin_start = nullptr;
+  int4* pieces = nullptr;
+  int32_t* n_pieces = nullptr;
+  BinRec* recs = nullptr;
+  int reduce_grid = 0;
+  double* sqerr = nullptr;
+  const float* vols = nullptr;
+  int32_t vol_n = 0;
   const float* proj = nullptr;
   int64_t step = 0;
   int64_t epoch_cached = -1;
@@ -178,8 +220,8 @@ struct nic_model {
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
-  double ms[5] = {0, 0, 0, 0, 0};
-  int64_t calls[5] = {0, 0, 0, 0, 0};
+  double ms[kKinds] = {};
+  int64_t calls[kKinds] = {};
 };
 
 namespace {
@@ -220,7 +262,7 @@ FwdArgs fwd_args(nic_model* m, int mode, int64_t n_points) {
   a.mode = mode;
   a.N = m->cfg.samples_per_ray;
   a.n_points = n_points;
-  a.table = m->params;
+  a.table = m->th ? (const void*)m->th : (const void*)m->params;
   a.dense = m->params + m->plan.dense_off;
   a.lt = m->plan.lt;
   a.geo = m->geo;
@@ -269,35 +311,75 @@ nic_status adam(nic_model* m) {
   return NIC_OK;
 }
 
-// Forward + backward (+ reduce) over the rays currently in m->rays.
-nic_status fwd_bwd(nic_model* m, int32_t n_rays, const float* jitter, const float* dA, float* loss_dev) {
-  const int64_t P = (int64_t)n_rays * m->cfg.samples_per_ray;
-  FwdArgs a = fwd_args(m, kModeRays, P);
-  a.jitter = jitter;
-  a.enc_out = m->enc;
-  a.wave_sum = m->wsum;
-  {
-    KTimer kt(m, 1);
-    NIC_HIP(launch_fwd(m->plan.ks, a, m->stream));
-  }
-  BwdArgs b{};
-  b.enc_in = m->enc;
-  b.dA_in = dA;
-  b.inv_R = 1.0f / (float)n_rays;
-  b.a_pred_out = m->apred;
-  b.absres_out = m->absres;
-  b.grad_table = m->grads;
-  b.partials = m->partials;
+// Forward + backward (+ reduces) over the points of `a` (rays or voxel-loss mode).  The forward pass
+// counts the table-gradient records per (bin, block); the scan turns the counts into write
+// offsets; the backward pass writes its records there; the bin reduction sums them into the table
+// gradient.  loss_src/loss_n/loss_scale: the per-ray (or per-wave) absolute residuals whose scaled
+// sum is the loss written to loss_dev (when not NULL).
+nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, int32_t loss_n, float loss_scale,
+                   float* loss_dev) {
+  const Plan& pl = m->plan;
+  const int64_t P = a.n_points;
   const int64_t chunks = (P + kPtsPerBlock - 1) / kPtsPerBlock;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, m->bwd_grid));
+  const size_t bin_lds = (size_t)pl.n_bins * 4;
+  a.enc_out = m->enc;
+  a.wave_sum = m->wsum;
+  a.bin_counts = m->counts;
+  a.n_bins = pl.n_bins;
+  {
+    KTimer kt(m, 1);
+    NIC_HIP(launch_fwd(pl.ks, a, grid, bin_lds, m->stream));
+  }
+  {
+    KTimer kt(m, 5);
+    NIC_HIP(launch_bin_scan(m->counts, pl.n_bins, grid, pl.dense_end, m->offs, m->totals, m->bin_start, m->pieces,
+                            m->n_pieces, m->stream));
+  }
+  b.enc_in = m->enc;
+  b.a_pred_out = m->apred;
+  b.absres_out = m->absres;
+  b.partials = m->partials;
+  b.bin_offsets = m->offs;
+  b.bin_start = m->bin_start;
+  b.recs = m->recs;
   {
     KTimer kt(m, 2);
-    NIC_HIP(launch_bwd(m->plan.ks, a, b, grid, m->stream));
+    NIC_HIP(launch_bwd(pl.ks, a, b, grid, bin_lds, m->stream));
+  }
+  {
+    KTimer kt(m, 6);
+    NIC_HIP(launch_bin_reduce(m->recs, m->pieces, m->n_pieces, m->grads, pl.n_entries * pl.n_tables,
+                              m->reduce_grid, m->stream));
   }
   KTimer kt(m, 3);
-  NIC_HIP(launch_reduce(m->partials, grid, m->plan.nd_pad, (int)m->plan.n_dense, m->grads + m->plan.dense_off,
-                        m->absres, n_rays, 1.0f / (float)n_rays, dA ? nullptr : loss_dev, m->stream));
+  NIC_HIP(launch_reduce(m->partials, grid, pl.nd_pad, (int)pl.n_dense, m->grads + pl.dense_off, loss_src, loss_n,
+                        loss_scale, loss_dev, m->stream));
   return NIC_OK;
+}
+
+// Ray training pass over the rays currently in m->rays (dA == NULL: L1 loss of Eq. 3).
+nic_status ray_fwd_bwd(nic_model* m, int32_t n_rays, const float* jitter, const float* dA, float* loss_dev) {
+  FwdArgs a = fwd_args(m, kModeRays, (int64_t)n_rays * m->cfg.samples_per_ray);
+  a.jitter = jitter;
+  BwdArgs b{};
+  b.dA_in = dA;
+  b.inv_R = 1.0f / (float)n_rays;
+  return fwd_bwd(m, a, b, m->absres, n_rays, 1.0f / (float)n_rays, dA ? nullptr : loss_dev);
+}
+
+// Voxel-loss pass (Eq. 2) over n_points points.
+nic_status voxel_fwd_bwd(nic_model* m, const float* xn, int32_t n_points, float* loss_dev) {
+  FwdArgs a = fwd_args(m, kModeVoxelLoss, n_points);
+  a.xn = xn;
+  a.pts_per_table = n_points / m->plan.n_tables;
+  a.table_stride = (uint32_t)m->plan.n_entries;
+  a.vols = m->vols;
+  a.vol_n = m->vol_n;
+  BwdArgs b{};
+  b.inv_R = 1.0f / (float)n_points;
+  b.wave_loss = m->wsum;
+  return fwd_bwd(m, a, b, m->wsum, n_points / kPtsPerWave, 1.0f / (float)n_points, loss_dev);
 }
 
 bool model_ok(const nic_model* m) { return m != nullptr && m->ws != nullptr; }
@@ -386,15 +468,24 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipFuncSetAttribute(p.ks.fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.ks.fwd_lds);
-  if (e == hipSuccess) e = hipFuncSetAttribute(p.ks.bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.ks.bwd_lds);
-  int per_cu = 0;
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.ks.bwd, kBlock, p.ks.bwd_lds);
+  const size_t bin_lds = (size_t)p.n_bins * 4;
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(p.ks.fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(p.ks.fwd_lds + bin_lds));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(p.ks.bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(p.ks.bwd_lds + bin_lds));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(bin_reduce_kernel(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bin_reduce_lds());
+  int per_cu = 0, per_cu_red = 0;
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.ks.bwd, kBlock, p.ks.bwd_lds + bin_lds);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_red, bin_reduce_kernel(), 1024, bin_reduce_lds());
   if (e != hipSuccess) {
     delete m;
     return fail(NIC_EHIP, "device query: %s", hipGetErrorString(e));
   }
   m->bwd_grid = std::max(1, std::min(kMaxBwdBlocks, m->n_cu * std::max(1, per_cu)));
+  m->reduce_grid = std::max(1, m->n_cu * std::max(1, per_cu_red));
 
   char* ws = (char*)workspace;
   m->ws = ws;
@@ -411,6 +502,14 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   m->absres = (float*)(ws + p.o_absres);
   m->loss = (float*)(ws + p.o_loss);
   m->pix = (int32_t*)(ws + p.o_pix);
+  m->counts = (uint32_t*)(ws + p.o_counts);
+  m->offs = (uint32_t*)(ws + p.o_offs);
+  m->pieces = (int4*)(ws + p.o_pieces);
+  m->n_pieces = (int32_t*)(ws + p.o_npieces);
+  m->recs = (BinRec*)(ws + p.o_recs);
+  m->totals = (uint32_t*)(ws + p.o_totals);
+  m->bin_start = (uint32_t*)(ws + p.o_binstart);
+  m->sqerr = (double*)(ws + p.o_sqerr);
   *out = m;
   const nic_status st = nic_init_params(m, cfg->seed);
   if (st != NIC_OK) {
@@ -434,7 +533,7 @@ void nic_destroy(nic_model* m) {
 nic_status nic_set_timing(nic_model* m, int32_t enable) {
   if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
   m->timing = enable != 0;
-  for (int k = 0; k < 5; ++k) { m->ms[k] = 0; m->calls[k] = 0; }
+  for (int k = 0; k < kKinds; ++k) { m->ms[k] = 0; m->calls[k] = 0; }
   return NIC_OK;
 }
 
@@ -450,8 +549,8 @@ nic_status nic_kernel_times(nic_model* m, double* ms, int64_t* calls, int32_t* c
     m->ev_free.push_back(pe.second.second);
   }
   m->ev_pending.clear();
-  for (int k = 0; k < 5; ++k) { ms[k] = m->ms[k]; calls[k] = m->calls[k]; }
-  *count = 5;
+  for (int k = 0; k < kKinds; ++k) { ms[k] = m->ms[k]; calls[k] = m->calls[k]; }
+  *count = kKinds;
   return NIC_OK;
 }
 
@@ -531,7 +630,7 @@ nic_status nic_step(nic_model* m, int32_t view, const int32_t* pix_dev, const fl
   const int32_t R = m->cfg.rays_per_step;
   nic_status st = rays(m, view, pix_dev, R, (uint32_t)m->step, nullptr, nullptr);
   if (st) return st;
-  st = fwd_bwd(m, R, jitter_dev, nullptr, loss_dev ? loss_dev : m->loss);
+  st = ray_fwd_bwd(m, R, jitter_dev, nullptr, loss_dev ? loss_dev : m->loss);
   if (st) return st;
   return adam(m);
 }
@@ -547,7 +646,7 @@ nic_status nic_train(nic_model* m, int32_t n_steps, float* loss_host) {
       const int32_t view = nic_view_for_step(m, m->step);
       nic_status st = rays(m, view, nullptr, m->cfg.rays_per_step, (uint32_t)m->step, nullptr, nullptr);
       if (st) return st;
-      st = fwd_bwd(m, m->cfg.rays_per_step, nullptr, nullptr, m->loss + k);
+      st = ray_fwd_bwd(m, m->cfg.rays_per_step, nullptr, nullptr, m->loss + k);
       if (st) return st;
       st = adam(m);
       if (st) return st;
@@ -576,7 +675,7 @@ nic_status nic_forward(nic_model* m, int32_t view, const int32_t* pix_dev, const
   FwdArgs a = fwd_args(m, kModeRays, P);
   a.jitter = jitter_dev;
   a.wave_sum = m->wsum;
-  NIC_HIP(launch_fwd(m->plan.ks, a, m->stream));
+  NIC_HIP(launch_fwd(m->plan.ks, a, 0, 0, m->stream));
   NIC_HIP(launch_raysum(m->wsum, m->cfg.samples_per_ray / kPtsPerWave, n_rays, a_pred_dev, m->stream));
   return NIC_OK;
 }
@@ -590,7 +689,7 @@ nic_status nic_backward(nic_model* m, int32_t view, const int32_t* pix_dev, cons
   if (n_rays == 0) return NIC_OK;
   nic_status st = rays(m, view, pix_dev, n_rays, (uint32_t)m->step, nullptr, nullptr);
   if (st) return st;
-  return fwd_bwd(m, n_rays, jitter_dev, dA_dev, nullptr);
+  return ray_fwd_bwd(m, n_rays, jitter_dev, dA_dev, nullptr);
 }
 
 nic_status nic_adam(nic_model* m) {
@@ -612,7 +711,7 @@ nic_status nic_query(nic_model* m, const float* xn_dev, int64_t n, float* mu_dev
   FwdArgs a = fwd_args(m, kModePoints, n);
   a.xn = xn_dev;
   a.mu_out = mu_dev;
-  NIC_HIP(launch_fwd(m->plan.ks, a, m->stream));
+  NIC_HIP(launch_fwd(m->plan.ks, a, 0, 0, m->stream));
   return NIC_OK;
 }
 
@@ -624,7 +723,7 @@ nic_status nic_render_volume(nic_model* m, const int32_t dims[3], float* vol_dev
   FwdArgs a = fwd_args(m, kModeVoxels, n);
   for (int k = 0; k < 3; ++k) a.dims[k] = dims[k];
   a.mu_out = vol_dev;
-  NIC_HIP(launch_fwd(m->plan.ks, a, m->stream));
+  NIC_HIP(launch_fwd(m->plan.ks, a, 0, 0, m->stream));
   return NIC_OK;
 }
 
@@ -633,7 +732,123 @@ nic_status nic_encode(nic_model* m, const float* xn_dev, int64_t n, float* enc_d
   if (n < 0) return fail(NIC_EINVAL, "n must be >= 0");
   if (n == 0) return NIC_OK;
   if (!xn_dev || !enc_dev) return fail(NIC_EINVAL, "NULL argument");
-  NIC_HIP(launch_encode(m->plan.lt, m->params, xn_dev, n, enc_dev, idx_dev, m->stream));
+  NIC_HIP(launch_encode(m->plan.lt, m->th ? (const void*)m->th : (const void*)m->params, m->th ? 1 : 0, xn_dev, n,
+                        enc_dev, idx_dev, m->stream));
+  return NIC_OK;
+}
+
+nic_status nic_set_volumes(nic_model* m, const float* vols_dev, int32_t n) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (!vols_dev || n < 2 || n > 2048) return fail(NIC_EINVAL, "need volumes and 2 <= n <= 2048");
+  m->vols = vols_dev;
+  m->vol_n = n;
+  return NIC_OK;
+}
+
+static nic_status check_voxel_args(nic_model* m, int32_t n_points) {
+  const int32_t K = m->plan.n_tables;
+  if (!m->vols) return fail(NIC_ESTATE, "target volumes not set");
+  if (n_points < 32 * K || n_points % (32 * K))
+    return fail(NIC_EINVAL, "n_points must be a positive multiple of 32 * n_tables");
+  if ((int64_t)n_points > (int64_t)m->cfg.rays_per_step * m->cfg.samples_per_ray)
+    return fail(NIC_EINVAL, "n_points exceeds rays_per_step * samples_per_ray");
+  return NIC_OK;
+}
+
+nic_status nic_voxel_step(nic_model* m, const float* xn_dev, int32_t n_points, float* loss_dev) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  nic_status st = check_voxel_args(m, n_points);
+  if (st) return st;
+  st = voxel_fwd_bwd(m, xn_dev, n_points, loss_dev ? loss_dev : m->loss);
+  if (st) return st;
+  return adam(m);
+}
+
+nic_status nic_voxel_train(nic_model* m, int32_t n_steps, int32_t n_points, float* loss_host) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (n_steps < 0) return fail(NIC_EINVAL, "n_steps must be >= 0");
+  nic_status st = check_voxel_args(m, n_points);
+  if (st) return st;
+  bool bad = false;
+  for (int32_t k0 = 0; k0 < n_steps; k0 += kLossHist) {
+    const int32_t kn = std::min<int32_t>(kLossHist, n_steps - k0);
+    for (int32_t k = 0; k < kn; ++k) {
+      st = voxel_fwd_bwd(m, nullptr, n_points, m->loss + k);
+      if (st) return st;
+      st = adam(m);
+      if (st) return st;
+    }
+    if (loss_host) {
+      NIC_HIP(hipMemcpyAsync(loss_host + k0, m->loss, kn * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+      NIC_HIP(hipStreamSynchronize(m->stream));
+      for (int32_t k = 0; k < kn; ++k)
+        if (!std::isfinite(loss_host[k0 + k])) bad = true;
+    }
+  }
+  if (bad) return fail(NIC_ENONFINITE, "non-finite loss");
+  return NIC_OK;
+}
+
+nic_status nic_export_mlp(nic_model* m, void* buf, size_t* bytes) {
+  if (!model_ok(m) || !bytes) return fail(NIC_EINVAL, "NULL argument");
+  const size_t need = sizeof(MlpBlobHeader) + (size_t)m->plan.n_dense * sizeof(float);
+  if (!buf) {
+    *bytes = need;
+    return NIC_OK;
+  }
+  if (*bytes < need) return fail(NIC_EINVAL, "buffer too small (%zu < %zu)", *bytes, need);
+  MlpBlobHeader h{};
+  memcpy(h.magic, "NICM", 4);
+  h.version = kBlobVersion;
+  h.channels = m->plan.C;
+  h.width = m->cfg.mlp_width;
+  h.depth = m->cfg.mlp_depth;
+  h.out_act = m->cfg.out_act;
+  h.layernorm = m->cfg.layernorm;
+  h.n_dense = (int32_t)m->plan.n_dense;
+  h.mu_max = m->cfg.mu_max;
+  h.ln_eps = m->cfg.ln_eps;
+  memcpy(buf, &h, sizeof h);
+  NIC_HIP(hipMemcpyAsync((char*)buf + sizeof h, m->params + m->plan.dense_off, (size_t)m->plan.n_dense * 4,
+                         hipMemcpyDeviceToHost, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  *bytes = need;
+  return NIC_OK;
+}
+
+nic_status nic_import_mlp(nic_model* m, const void* buf, size_t bytes) {
+  if (!model_ok(m) || !buf) return fail(NIC_EINVAL, "NULL argument");
+  if (bytes < sizeof(MlpBlobHeader)) return fail(NIC_EVERSION, "blob too short");
+  MlpBlobHeader h;
+  memcpy(&h, buf, sizeof h);
+  if (memcmp(h.magic, "NICM", 4) || h.version != kBlobVersion) return fail(NIC_EVERSION, "not an MLP blob");
+  if (h.channels != m->plan.C || h.width != m->cfg.mlp_width || h.depth != m->cfg.mlp_depth ||
+      h.out_act != m->cfg.out_act || h.layernorm != m->cfg.layernorm || h.n_dense != m->plan.n_dense)
+    return fail(NIC_EVERSION, "blob of another network shape");
+  if (bytes < sizeof h + (size_t)h.n_dense * 4) return fail(NIC_EVERSION, "blob truncated");
+  NIC_HIP(hipMemcpyAsync(m->params + m->plan.dense_off, (const char*)buf + sizeof h, (size_t)h.n_dense * 4,
+                         hipMemcpyHostToDevice, m->stream));
+  NIC_HIP(launch_fill(m->m + m->plan.dense_off, m->plan.n_dense, 0.0f, m->n_cu, m->stream));
+  NIC_HIP(launch_fill(m->v + m->plan.dense_off, m->plan.n_dense, 0.0f, m->n_cu, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  return NIC_OK;
+}
+
+nic_status nic_psnr(nic_model* m, const float* gt_dev, const float* pred_dev, int64_t n, double* psnr_host) {
+  if (!model_ok(m) || !gt_dev || !pred_dev || !psnr_host) return fail(NIC_EINVAL, "NULL argument");
+  if (n < 1) return fail(NIC_EINVAL, "n must be >= 1");
+  const int nb = (int)std::min<int64_t>(kSqerrBlocks, (n + 255) / 256);
+  NIC_HIP(launch_sqerr(gt_dev, pred_dev, n, m->sqerr, nb, m->stream));
+  std::vector<double> h(2 * (size_t)nb);
+  NIC_HIP(hipMemcpyAsync(h.data(), m->sqerr, h.size() * 8, hipMemcpyDeviceToHost, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  double se = 0.0, mx = -1e300;
+  for (int b = 0; b < nb; ++b) {
+    se += h[2 * b];
+    mx = std::max(mx, h[2 * b + 1]);
+  }
+  const double mse = se / (double)n;
+  *psnr_host = mse == 0.0 ? INFINITY : 10.0 * std::log10(mx * mx / mse);
   return NIC_OK;
 }
 

@@ -15,6 +15,14 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kPtsPerBlock = kPtsPerWave * kWavesPerBlock;
 constexpr int kTile = 33;            // padded row length of the per-wave LDS transpose tiles
+constexpr int kBinBits = 13;         // table-gradient bins of 2^13 entries (64 KB of FP32 x 2 in LDS)
+constexpr int kPiece = 1 << 16;      // records reduced by one block in one pass
+
+// One corner contribution to the table gradient: entry and the two feature gradients.
+struct BinRec {
+  uint32_t idx;
+  float v0, v1;
+};
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -148,6 +156,39 @@ __device__ inline void sample_pos(const Geo& g, const RayRec& r, int i, float u,
   }
 }
 
+// Point p of step `step` for the voxel loss: three 24-bit uniforms from one Philox block.
+__device__ inline void voxel_point(uint64_t seed, uint32_t step, uint32_t p, float x[3]) {
+  uint32_t c[4] = {p, step, 0u, kPoints};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  x[0] = u24f(c[0]);
+  x[1] = u24f(c[1]);
+  x[2] = u24f(c[2]);
+}
+
+// Trilinear sample of vol[z][y][x] (n^3 voxels, centres at (i + 1/2)/n) at a normalised point:
+// continuous index u = x n - 1/2 clamped to [0, n - 1], base cell floor(u) clamped to n - 2.
+__device__ inline float trilinear(const float* __restrict__ vol, int n, const float x[3]) {
+  int b[3];
+  float f[3];
+  for (int k = 0; k < 3; ++k) {
+    float u = x[k] * (float)n - 0.5f;
+    u = u < 0.0f ? 0.0f : u;
+    u = u > (float)(n - 1) ? (float)(n - 1) : u;
+    int i = (int)floorf(u);
+    i = i > n - 2 ? n - 2 : i;
+    i = i < 0 ? 0 : i;
+    b[k] = i;
+    f[k] = u - (float)i;
+  }
+  float s = 0.0f;
+  for (int c = 0; c < 8; ++c) {
+    const int c0 = c & 1, c1 = (c >> 1) & 1, c2 = (c >> 2) & 1;
+    const float w = (c0 ? f[0] : 1.0f - f[0]) * (c1 ? f[1] : 1.0f - f[1]) * (c2 ? f[2] : 1.0f - f[2]);
+    s += w * vol[((size_t)(b[2] + c2) * n + (b[1] + c1)) * n + (b[0] + c0)];
+  }
+  return s;
+}
+
 // Normalised FP32 coordinate of voxel centre i of n along one axis.
 __device__ inline float voxel_coord(int i, int n) {
 #pragma clang fp contract(off)
@@ -179,8 +220,8 @@ __device__ __forceinline__ void cell_of(float x, int32_t N, uint32_t& g, float& 
 // Dense: off + v0 + s (v1 + s v2), s = N + 1.  Hashed: off + ((v0 * 1) ^ (v1 * 2654435761) ^
 // (v2 * 805459861)) & (T - 1) in uint32 arithmetic (Instant-NGP's spatial hash).
 __device__ __forceinline__ void level_corners(int32_t N, uint32_t off, uint32_t stride, uint32_t mask,
-                                              const float x[3], uint32_t idx[8], float w[8]) {
-  uint32_t g0, g1, g2;
+                                              const float x[3], uint32_t idx[8], float w[8], uint32_t& g0,
+                                              uint32_t& g1, uint32_t& g2) {
   float f0, f1, f2;
   cell_of(x[0], N, g0, f0);
   cell_of(x[1], N, g1, f1);
@@ -201,6 +242,22 @@ __device__ __forceinline__ void level_corners(int32_t N, uint32_t off, uint32_t 
   }
 #pragma unroll
   for (int c = 0; c < 8; ++c) w[c] = wx[c & 1] * wy[(c >> 1) & 1] * wz[(c >> 2) & 1];
+}
+
+__device__ __forceinline__ void level_corners(int32_t N, uint32_t off, uint32_t stride, uint32_t mask,
+                                              const float x[3], uint32_t idx[8], float w[8]) {
+  uint32_t g0, g1, g2;
+  level_corners(N, off, stride, mask, x, idx, w, g0, g1, g2);
+}
+
+// Runs along a ray: the 32 lanes of a half hold 32 consecutive samples of one ray, so samples that
+// share a cell of a coarse level form contiguous runs.  cont: this lane's cell equals the previous
+// lane's; tail: the next lane does not continue the run (the run's last lane).
+__device__ __forceinline__ void run_flags(uint32_t g0, uint32_t g1, uint32_t g2, int ln, bool& cont, bool& tail) {
+  const uint32_t p0 = __shfl_up(g0, 1, 32), p1 = __shfl_up(g1, 1, 32), p2 = __shfl_up(g2, 1, 32);
+  cont = ln > 0 && p0 == g0 && p1 == g1 && p2 == g2;
+  const int nc = __shfl_down((int)cont, 1, 32);
+  tail = !(ln < 31 && nc);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -9,13 +9,13 @@
 
 namespace nic {
 
-enum { kModeRays = 0, kModePoints = 1, kModeVoxels = 2 };
+enum { kModeRays = 0, kModePoints = 1, kModeVoxels = 2, kModeVoxelLoss = 3 };
 
 struct FwdArgs {
   int32_t mode;          // kModeRays / kModePoints / kModeVoxels
   int32_t N;             // samples per ray (rays mode)
   int64_t n_points;      // rays: n_rays * N
-  const float* table;    // FP32 table [n_entries][2]
+  const void* table;     // table gathered by the forward: FP32 [n_entries][2], or FP16 (precision 1)
   const float* dense;    // FP32 dense parameters (global layout)
   LevelTab lt;
   Geo geo;
@@ -32,6 +32,14 @@ struct FwdArgs {
   float* enc_out;        // rays mode: raw encoding, lane-major per wave (or NULL)
   float* wave_sum;       // rays mode: per-wave partial sums of mu * delta
   float* mu_out;         // points / voxels mode
+  uint32_t* bin_counts;  // training: [n_bins][gridDim] records per (bin, block), or NULL
+  int32_t n_bins;
+  // voxel-loss mode (pre-training): point p uses table p / pts_per_table, whose entries start at
+  // (p / pts_per_table) * table_stride, and the target volume of that table
+  int64_t pts_per_table;
+  uint32_t table_stride;
+  int32_t vol_n;
+  const float* vols;     // [n_tables][vol_n]^3
 };
 
 struct BwdArgs {
@@ -40,8 +48,11 @@ struct BwdArgs {
   float inv_R;           // 1/R for the mean over rays
   float* a_pred_out;     // [n_rays] (L1 mode)
   float* absres_out;     // [n_rays] (L1 mode)
-  float* grad_table;     // FP32 [n_entries][2]
   float* partials;       // [grid][nd_pad] per-block dense gradients
+  const uint32_t* bin_offsets;  // [n_bins][grid] first slot of each (bin, block) run within the bin
+  const uint32_t* bin_start;    // [n_bins] first record of each bin
+  BinRec* recs;          // table-gradient records grouped by bin
+  float* wave_loss;      // voxel-loss mode: per-wave sum of |mu - target|
 };
 
 struct RaysArgs {
@@ -79,8 +90,11 @@ struct KernelSet {
 };
 
 KernelSet kernel_set(int L, int W, int D, int precision);
-hipError_t launch_fwd(const KernelSet& ks, const FwdArgs& a, hipStream_t s);
-hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, int grid, hipStream_t s);
+// Forward: grid = min(chunks, max_grid) persistent blocks (max_grid <= 0: one block per chunk);
+// extra_lds = bytes of the bin histogram when counting.
+hipError_t launch_fwd(const KernelSet& ks, const FwdArgs& a, int max_grid, size_t extra_lds, hipStream_t s);
+hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, int grid, size_t extra_lds,
+                      hipStream_t s);
 hipError_t launch_rays(const RaysArgs& a, hipStream_t s);
 hipError_t launch_raysum(const float* wave_sum, int waves_per_ray, int n_rays, float* out, hipStream_t s);
 hipError_t launch_reduce(const float* partials, int n_blocks, int nd_pad, int nd, float* grad_dense,
@@ -91,7 +105,15 @@ hipError_t launch_fill(float* x, int64_t n, float val, int n_cu, hipStream_t s);
 hipError_t launch_to_half(const float* src, __half* dst, int64_t n, int n_cu, hipStream_t s);
 hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const InitArgs& ia, int n_cu,
                        hipStream_t s);
-hipError_t launch_encode(const LevelTab& lt, const float* table, const float* xn, int64_t n, float* enc,
-                         uint32_t* idx, hipStream_t s);
+hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t dense_end, uint32_t* rel,
+                           uint32_t* totals, uint32_t* bin_start, int4* pieces, int32_t* n_pieces, hipStream_t s);
+hipError_t launch_bin_reduce(const BinRec* recs, const int4* pieces, const int32_t* n_pieces, float* grad_table,
+                             int64_t n_entries, int grid, hipStream_t s);
+size_t bin_reduce_lds();
+const void* bin_reduce_kernel();
+hipError_t launch_sqerr(const float* gt, const float* pred, int64_t n, double* partials, int n_blocks,
+                        hipStream_t s);
+hipError_t launch_encode(const LevelTab& lt, const void* table, int half_table, const float* xn, int64_t n,
+                         float* enc, uint32_t* idx, hipStream_t s);
 
 }  // namespace nic

@@ -25,7 +25,7 @@ namespace nic {
 // [W][K_k + 1] so both the forward (row-varying) and backward (column-varying) MFMA operand reads
 // are free of bank conflicts.
 // ---------------------------------------------------------------------------------------------
-template <int C, int W, int D>
+template <int C, int W, int D, int P>
 struct Lay {
   static constexpr int K(int k) { return k == 0 ? C : W; }
   // global
@@ -37,29 +37,61 @@ struct Lay {
   }
   static constexpr int gb(int k) { return gW(k) + W * K(k); }
   static constexpr int g_wo = gW(D), g_bo = gW(D) + W, g_n = gW(D) + W + 1;
-  // LDS
+  // LDS, FP32 form: weights padded to [W][K+1] followed by the bias of each layer
   static constexpr int sW(int k) {
     int o = 0;
     for (int i = 0; i < k; ++i) o += W * (K(i) + 1) + W;
     return o;
   }
-  static constexpr int sb(int k) { return sW(k) + W * (K(k) + 1); }
-  static constexpr int s_lng = sW(D), s_lnb = sW(D) + C, s_wo = sW(D) + 2 * C, s_bo = sW(D) + 2 * C + W;
-  static constexpr int s_n = (sW(D) + 2 * C + W + 1 + 3) & ~3;
+  // LDS, BF16 form: MFMA operand blocks of 8 bf16 per lane (units of 4 floats), forward layout
+  // then transposed (backward) layout, followed by the FP32 biases
+  static constexpr int wf(int k) {
+    int o = 0;
+    for (int i = 0; i < k; ++i) o += (W / 32) * (K(i) / 16) * 64;
+    return o;
+  }
+  static constexpr int wb(int k) {
+    int o = wf(D);
+    for (int i = 0; i < k; ++i) o += ((K(i) + 31) / 32) * (W / 16) * 64;
+    return o;
+  }
+  static constexpr int n_w16 = wb(D);
+  static constexpr int sb(int k) { return P ? 4 * n_w16 + k * W : sW(k) + W * (K(k) + 1); }
+  static constexpr int s_small = P ? 4 * n_w16 + D * W : sW(D);
+  static constexpr int s_lng = s_small, s_lnb = s_small + C, s_wo = s_small + 2 * C, s_bo = s_small + 2 * C + W;
+  static constexpr int s_n = (s_small + 2 * C + W + 1 + 3) & ~3;
 };
 
-template <int C, int W, int D>
+template <int C, int W, int D, int P>
 __device__ void stage_params(const float* __restrict__ dense, float* __restrict__ sp) {
-  using Ly = Lay<C, W, D>;
+  using Ly = Lay<C, W, D, P>;
   const int t = threadIdx.x, nt = blockDim.x;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    constexpr int dummy = 0;
-    (void)dummy;
     const int Kk = Ly::K(k);
-    for (int e = t; e < W * (Kk + 1); e += nt) {
-      const int o = e / (Kk + 1), i = e - o * (Kk + 1);
-      sp[Ly::sW(k) + e] = (i < Kk) ? dense[Ly::gW(k) + o * Kk + i] : 0.0f;
+    if constexpr (P == 0) {
+      for (int e = t; e < W * (Kk + 1); e += nt) {
+        const int o = e / (Kk + 1), i = e - o * (Kk + 1);
+        sp[Ly::sW(k) + e] = (i < Kk) ? dense[Ly::gW(k) + o * Kk + i] : 0.0f;
+      }
+    } else {
+      __bf16* s16 = reinterpret_cast<__bf16*>(sp);
+      // forward blocks: unit (mb, s, lane) holds W[32mb + lane%32][chan(8s + i, lane/32)], i < 8
+      const int nf = (W / 32) * (Kk / 16) * 64 * 8;
+      for (int e = t; e < nf; e += nt) {
+        const int i = e & 7, q = e >> 3, lane = q & 63, ms = q >> 6;
+        const int s = ms % (Kk / 16), mb = ms / (Kk / 16);
+        const int o = 32 * mb + (lane & 31), col = chan(8 * s + i, lane >> 5);
+        s16[8 * Ly::wf(k) + e] = (__bf16)dense[Ly::gW(k) + o * Kk + col];
+      }
+      // backward blocks: unit (ib, s, lane) holds W[chan(8s + i, lane/32)][32ib + lane%32]
+      const int nb = ((Kk + 31) / 32) * (W / 16) * 64 * 8;
+      for (int e = t; e < nb; e += nt) {
+        const int i = e & 7, q = e >> 3, lane = q & 63, is = q >> 6;
+        const int s = is % (W / 16), ib = is / (W / 16);
+        const int o = chan(8 * s + i, lane >> 5), col = 32 * ib + (lane & 31);
+        s16[8 * Ly::wb(k) + e] = (col < Kk) ? (__bf16)dense[Ly::gW(k) + o * Kk + col] : (__bf16)0.0f;
+      }
     }
     for (int e = t; e < W; e += nt) sp[Ly::sb(k) + e] = dense[Ly::gb(k) + e];
   }
@@ -77,9 +109,10 @@ __device__ void stage_params(const float* __restrict__ dense, float* __restrict_
 
 // Encoding of the levels handled by lane half h: register r = 4j + 2q + f holds feature f of level
 // 4j + 2h + q, i.e. channel chan(r, h).
-template <int L>
-__device__ __forceinline__ void encode_half(const LevelTab& T, const float2* __restrict__ table,
-                                            const float x[3], int h, float e[L]) {
+template <int L, int P>
+__device__ __forceinline__ void encode_half(const LevelTab& T, const void* __restrict__ table_,
+                                            const float x[3], int h, float e[L], bool count, uint32_t* hist,
+                                            int ln, uint32_t tbase) {
 #pragma unroll
   for (int j = 0; j < L / 4; ++j) {
 #pragma unroll
@@ -90,24 +123,39 @@ __device__ __forceinline__ void encode_half(const LevelTab& T, const float2* __r
       const uint32_t st = h ? T.stride[lB] : T.stride[lA];
       uint32_t idx[8];
       float w[8];
-      level_corners(N, off, st, T.mask, x, idx, w);
+      uint32_t g0, g1, g2;
+      level_corners(N, off + tbase, st, T.mask, x, idx, w, g0, g1, g2);
       float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const float2 v = table[idx[c]];
+        float2 v;
+        if constexpr (P == 0) v = reinterpret_cast<const float2*>(table_)[idx[c]];
+        else v = __half22float2(reinterpret_cast<const __half2*>(table_)[idx[c]]);
         s0 += w[c] * v.x;
         s1 += w[c] * v.y;
       }
       e[4 * j + 2 * q] = s0;
       e[4 * j + 2 * q + 1] = s1;
+      if (count) {   // wave-uniform: the backward pass writes one record per corner per run
+        bool cont, tail;
+        run_flags(g0, g1, g2, ln, cont, tail);
+        if (tail && hist) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) atomicAdd(hist + (idx[c] >> kBinBits), 1u);
+        }
+      }
     }
   }
 }
 
-// Scatter-add of the channel gradients gx (same layout as encode_half) into the table gradient.
+// Corner contributions of the channel gradients gx (same layout as encode_half) as records
+// (entry, w * g_f0, w * g_f1), each written at the next slot of this block's run for the entry's bin.
+// Consecutive samples of the ray in the same cell (runs) share their 8 corner entries: a segmented
+// scan over the half sums each run and only the run's last lane writes the 8 records.
 template <int L>
-__device__ __forceinline__ void scatter_half(const LevelTab& T, float* __restrict__ gtab,
-                                             const float x[3], int h, const float gx[L]) {
+__device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restrict__ recs, uint32_t* cursor,
+                                             const float x[3], int h, const float gx[L], bool active, int ln,
+                                             uint32_t tbase) {
 #pragma unroll
   for (int j = 0; j < L / 4; ++j) {
 #pragma unroll
@@ -118,12 +166,46 @@ __device__ __forceinline__ void scatter_half(const LevelTab& T, float* __restric
       const uint32_t st = h ? T.stride[lB] : T.stride[lA];
       uint32_t idx[8];
       float w[8];
-      level_corners(N, off, st, T.mask, x, idx, w);
-      const float g0 = gx[4 * j + 2 * q], g1 = gx[4 * j + 2 * q + 1];
+      uint32_t g0, g1, g2;
+      level_corners(N, off + tbase, st, T.mask, x, idx, w, g0, g1, g2);
+      const float g0v = gx[4 * j + 2 * q], g1v = gx[4 * j + 2 * q + 1];
+      float v0[8], v1[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        atomicAdd(gtab + 2 * (size_t)idx[c], w[c] * g0);
-        atomicAdd(gtab + 2 * (size_t)idx[c] + 1, w[c] * g1);
+        v0[c] = w[c] * g0v;
+        v1[c] = w[c] * g1v;
+      }
+      bool cont, tail;
+      run_flags(g0, g1, g2, ln, cont, tail);
+      if (__ballot(cont) != 0) {            // wave-uniform: some lane continues a run
+        int start = cont ? 0 : ln;          // first lane of this lane's run (max-scan of run heads)
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+          const int t = __shfl_up(start, o, 32);
+          if (ln >= o && t > start) start = t;
+        }
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const float a0 = __shfl_up(v0[c], o, 32), a1 = __shfl_up(v1[c], o, 32);
+            if (ln - o >= start) {
+              v0[c] += a0;
+              v1[c] += a1;
+            }
+          }
+        }
+      }
+      if (active && tail) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const uint32_t slot = atomicAdd(cursor + (idx[c] >> kBinBits), 1u);
+          BinRec r;
+          r.idx = idx[c];
+          r.v0 = v0[c];
+          r.v1 = v1[c];
+          recs[slot] = r;
+        }
       }
     }
   }
@@ -208,6 +290,80 @@ __device__ __forceinline__ void layer_bwd_data(const float* __restrict__ sW, con
   for (int R = 0; R < KIN / 2; ++R) gin[R] = acc[R >> 4][R & 15];
 }
 
+// BF16 form of layer_fwd: v_mfma_f32_32x32x16_bf16, B operand = 8 consecutive registers of the lane
+// (channels chan(8s + i, h)) rounded to bf16, A operand = one pre-arranged bf16x8 block per lane.
+template <int K, int W>
+__device__ __forceinline__ void layer_fwd_bf16(const bf16x8* __restrict__ wf, const float* __restrict__ sb,
+                                               const float* xin, float* out, int lane) {
+  const int h = lane >> 5;
+  f32x16 acc[W / 32];
+#pragma unroll
+  for (int mb = 0; mb < W / 32; ++mb) acc[mb] = f32x16{};
+#pragma unroll
+  for (int s = 0; s < K / 16; ++s) {
+    bf16x8 b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = (__bf16)xin[8 * s + i];
+#pragma unroll
+    for (int mb = 0; mb < W / 32; ++mb) acc[mb] = mfma32_bf16(wf[(mb * (K / 16) + s) * 64 + lane], b, acc[mb]);
+  }
+#pragma unroll
+  for (int R = 0; R < W / 2; ++R) {
+    const float a = acc[R >> 4][R & 15] + sb[chan(R, h)];
+    out[R] = a > 0.0f ? a : 0.0f;
+  }
+}
+
+template <int KIN, int W>
+__device__ __forceinline__ void layer_bwd_data_bf16(const bf16x8* __restrict__ wb, const float* g, float* gin,
+                                                    int lane) {
+  constexpr int IB = (KIN + 31) / 32;
+  f32x16 acc[IB];
+#pragma unroll
+  for (int ib = 0; ib < IB; ++ib) acc[ib] = f32x16{};
+#pragma unroll
+  for (int s = 0; s < W / 16; ++s) {
+    bf16x8 b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = (__bf16)g[8 * s + i];
+#pragma unroll
+    for (int ib = 0; ib < IB; ++ib) acc[ib] = mfma32_bf16(wb[(ib * (W / 16) + s) * 64 + lane], b, acc[ib]);
+  }
+#pragma unroll
+  for (int R = 0; R < KIN / 2; ++R) gin[R] = acc[R >> 4][R & 15];
+}
+
+// bf16 tile [32 rows][kTile16] (row = channel, column = point) for the weight-gradient MFMA.
+constexpr int kTile16 = 40;
+
+template <int NREG>
+__device__ __forceinline__ void tile_put_bf16(__bf16* tile, const float* v, int blk, int lane) {
+  const int n = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int R = 16 * blk + r;
+    if (R < NREG) tile[chan(r, h) * kTile16 + n] = (__bf16)v[R];
+  }
+}
+
+// BF16 form of tile_outer_add: K = 32 points in two steps of 16.
+__device__ __forceinline__ void tile_outer_add_bf16(const __bf16* tG, const __bf16* tH, float* acc, int wbase,
+                                                    int K, int mb, int nb, int lane) {
+  const int m = lane & 31, h = lane >> 5;
+  f32x16 d = f32x16{};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(tG + m * kTile16 + 16 * s + 8 * h);
+    const bf16x8 bb = *reinterpret_cast<const bf16x8*>(tH + m * kTile16 + 16 * s + 8 * h);
+    d = mfma32_bf16(a, bb, d);
+  }
+  const int col = 32 * nb + m;
+  if (col < K) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) atomicAdd(acc + wbase + (32 * mb + chan(r, h)) * K + col, d[r]);
+  }
+}
+
 // Writes rows [32*blk, 32*blk + 32) of a per-point vector (n registers, layout chan) into a
 // [32][kTile] tile with column = point.
 template <int NREG>
@@ -268,10 +424,12 @@ __device__ __forceinline__ void point_position(const FwdArgs& a, int64_t p, bool
       const float u = a.jitter ? a.jitter[ray * a.N + i] : jitter(a.seed, a.step, (uint32_t)ray, (uint32_t)i);
       sample_pos(a.geo, rr, i, u, x);
     }
-  } else if (a.mode == kModePoints) {
+  } else if (a.mode == kModePoints || (a.mode == kModeVoxelLoss && a.xn)) {
     x[0] = a.xn[3 * p];
     x[1] = a.xn[3 * p + 1];
     x[2] = a.xn[3 * p + 2];
+  } else if (a.mode == kModeVoxelLoss) {
+    voxel_point(a.seed, a.step, (uint32_t)p, x);
   } else {
     const int64_t nxy = (int64_t)a.dims[0] * a.dims[1];
     const int iz = (int)(p / nxy);
@@ -284,68 +442,98 @@ __device__ __forceinline__ void point_position(const FwdArgs& a, int64_t p, bool
   }
 }
 
+// MLP forward of one point (hidden activations kept for the backward pass).
+template <int C, int W, int D, int P>
+__device__ __forceinline__ void mlp_forward(const float* sp, const float* z, float (&hb)[D][W / 2], int lane) {
+  using Ly = Lay<C, W, D, P>;
+  if constexpr (P == 0) {
+    layer_fwd<C, W>(sp + Ly::sW(0), sp + Ly::sb(0), z, hb[0], lane);
+#pragma unroll
+    for (int k = 1; k < D; ++k) layer_fwd<W, W>(sp + Ly::sW(k), sp + Ly::sb(k), hb[k - 1], hb[k], lane);
+  } else {
+    const bf16x8* w16 = reinterpret_cast<const bf16x8*>(sp);
+    layer_fwd_bf16<C, W>(w16 + Ly::wf(0), sp + Ly::sb(0), z, hb[0], lane);
+#pragma unroll
+    for (int k = 1; k < D; ++k) layer_fwd_bf16<W, W>(w16 + Ly::wf(k), sp + Ly::sb(k), hb[k - 1], hb[k], lane);
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Forward kernel
 // ---------------------------------------------------------------------------------------------
-template <int L, int W, int D>
+template <int L, int W, int D, int P>
 __global__ void __launch_bounds__(kBlock) k_fwd(const FwdArgs a) {
   constexpr int C = 2 * L, RC = C / 2, RW = W / 2;
-  using Ly = Lay<C, W, D>;
+  using Ly = Lay<C, W, D, P>;
   extern __shared__ float smem[];
   float* sp = smem;
-  stage_params<C, W, D>(a.dense, sp);
+  uint32_t* hist = a.bin_counts ? reinterpret_cast<uint32_t*>(smem + Ly::s_n) : nullptr;
+  stage_params<C, W, D, P>(a.dense, sp);
+  if (hist)
+    for (int b2 = threadIdx.x; b2 < a.n_bins; b2 += blockDim.x) hist[b2] = 0u;
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
-  const int64_t wave_id = (int64_t)blockIdx.x * kWavesPerBlock + wv;
-  const int64_t p = wave_id * kPtsPerWave + n;
-  const bool valid = p < a.n_points;
-  int64_t ray = 0;
-  int i = 0;
-  RayRec rr{};
-  if (a.mode == kModeRays && wave_id * kPtsPerWave < a.n_points) {
-    ray = (wave_id * kPtsPerWave) / a.N;
-    i = (int)(p - ray * a.N);
-    rr = a.rays[ray];
+  const int64_t n_chunks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
+  for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+    const int64_t wave_id = chunk * kWavesPerBlock + wv;
+    const int64_t p = wave_id * kPtsPerWave + n;
+    const bool wave_valid = wave_id * kPtsPerWave < a.n_points;
+    const bool valid = p < a.n_points;
+    int64_t ray = 0;
+    int i = 0;
+    RayRec rr{};
+    if (a.mode == kModeRays && wave_valid) {
+      ray = (wave_id * kPtsPerWave) / a.N;
+      i = (int)(p - ray * a.N);
+      rr = a.rays[ray];
+    }
+    float x[3];
+    point_position(a, p, valid, ray, i, rr, x);
+    const bool vloss = a.mode == kModeVoxelLoss;
+    const uint32_t tbase = vloss ? (uint32_t)(p / a.pts_per_table) * a.table_stride : 0u;
+
+    float e[RC];
+    // the bin histogram counts exactly the records the backward pass writes (hit rays only)
+    encode_half<L, P>(a.lt, a.table, x, h, e, hist != nullptr, (valid && (rr.hit || vloss)) ? hist : nullptr, n,
+                      tbase);
+    if (a.enc_out && wave_valid) {
+#pragma unroll
+      for (int r = 0; r < RC; ++r) a.enc_out[(wave_id * RC + r) * kWave + lane] = e[r];
+    }
+    float xh[RC], z[RC], rstd;
+    ln_forward<C>(e, sp + Ly::s_lng, sp + Ly::s_lnb, a.ln_eps, a.layernorm, h, xh, z, rstd);
+
+    float hb[D][RW];
+    mlp_forward<C, W, D, P>(sp, z, hb, lane);
+    float yp = 0.0f;
+#pragma unroll
+    for (int R = 0; R < RW; ++R) yp += sp[Ly::s_wo + chan(R, h)] * hb[D - 1][R];
+    const float y = yp + xor32(yp) + sp[Ly::s_bo];
+    const float mu = act_fwd(a.out_act, a.mu_max, y);
+
+    if (a.mode == kModeRays) {
+      float c = (h == 0 && valid) ? mu * rr.delta : 0.0f;
+      c = half_sum(c);
+      if (lane == 0 && wave_valid) a.wave_sum[wave_id] = c;
+    } else if (!vloss && h == 0 && valid) {
+      a.mu_out[p] = mu;
+    }
   }
-  float x[3];
-  point_position(a, p, valid, ray, i, rr, x);
-
-  float e[RC];
-  encode_half<L>(a.lt, reinterpret_cast<const float2*>(a.table), x, h, e);
-  if (a.enc_out && wave_id * kPtsPerWave < a.n_points) {
-#pragma unroll
-    for (int r = 0; r < RC; ++r) a.enc_out[(wave_id * RC + r) * kWave + lane] = e[r];
-  }
-  float xh[RC], z[RC], rstd;
-  ln_forward<C>(e, sp + Ly::s_lng, sp + Ly::s_lnb, a.ln_eps, a.layernorm, h, xh, z, rstd);
-
-  float hb[D][RW];
-  layer_fwd<C, W>(sp + Ly::sW(0), sp + Ly::sb(0), z, hb[0], lane);
-#pragma unroll
-  for (int k = 1; k < D; ++k) layer_fwd<W, W>(sp + Ly::sW(k), sp + Ly::sb(k), hb[k - 1], hb[k], lane);
-  float yp = 0.0f;
-#pragma unroll
-  for (int R = 0; R < RW; ++R) yp += sp[Ly::s_wo + chan(R, h)] * hb[D - 1][R];
-  const float y = yp + xor32(yp) + sp[Ly::s_bo];
-  const float mu = act_fwd(a.out_act, a.mu_max, y);
-
-  if (a.mode == kModeRays) {
-    float c = (h == 0 && valid) ? mu * rr.delta : 0.0f;
-    c = half_sum(c);
-    if (lane == 0 && wave_id * kPtsPerWave < a.n_points) a.wave_sum[wave_id] = c;
-  } else if (h == 0 && valid) {
-    a.mu_out[p] = mu;
+  if (hist) {
+    __syncthreads();
+    for (int b2 = threadIdx.x; b2 < a.n_bins; b2 += blockDim.x)
+      a.bin_counts[(size_t)b2 * gridDim.x + blockIdx.x] = hist[b2];
   }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Backward kernel (persistent over 128-point chunks)
 // ---------------------------------------------------------------------------------------------
-template <int L, int W, int D>
+template <int L, int W, int D, int P>
 __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b) {
   constexpr int C = 2 * L, RC = C / 2, RW = W / 2;
-  using Ly = Lay<C, W, D>;
+  using Ly = Lay<C, W, D, P>;
   extern __shared__ float smem[];
   float* sp = smem;
   float* acc = smem + Ly::s_n;
@@ -353,9 +541,12 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
   float* tG = acc + nd_pad + wv * (2 * 32 * kTile);
   float* tH = tG + 32 * kTile;
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(acc + nd_pad + kWavesPerBlock * 2 * 32 * kTile);
 
-  stage_params<C, W, D>(a.dense, sp);
+  stage_params<C, W, D, P>(a.dense, sp);
   for (int e2 = threadIdx.x; e2 < nd_pad; e2 += blockDim.x) acc[e2] = 0.0f;
+  for (int b2 = threadIdx.x; b2 < a.n_bins; b2 += blockDim.x)
+    cursor[b2] = b.bin_start[b2] + b.bin_offsets[(size_t)b2 * gridDim.x + blockIdx.x];
   __syncthreads();
 
   const int waves_per_ray = a.N / kPtsPerWave;
@@ -368,13 +559,16 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
     int64_t ray = 0;
     int i = 0;
     RayRec rr{};
-    if (wave_valid) {
+    const bool vloss = a.mode == kModeVoxelLoss;
+    if (wave_valid && !vloss) {
       ray = (wave_id * kPtsPerWave) / a.N;
       i = (int)(p - ray * a.N);
       rr = a.rays[ray];
     }
     float x[3];
     point_position(a, p, valid, ray, i, rr, x);
+    const uint32_t tid = vloss ? (uint32_t)(p / a.pts_per_table) : 0u;
+    const uint32_t tbase = tid * a.table_stride;
 
     float e[RC];
 #pragma unroll
@@ -383,17 +577,23 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
     ln_forward<C>(e, sp + Ly::s_lng, sp + Ly::s_lnb, a.ln_eps, a.layernorm, h, xh, z, rstd);
 
     float hb[D][RW];
-    layer_fwd<C, W>(sp + Ly::sW(0), sp + Ly::sb(0), z, hb[0], lane);
-#pragma unroll
-    for (int k = 1; k < D; ++k) layer_fwd<W, W>(sp + Ly::sW(k), sp + Ly::sb(k), hb[k - 1], hb[k], lane);
+    mlp_forward<C, W, D, P>(sp, z, hb, lane);
     float yp = 0.0f;
 #pragma unroll
     for (int R = 0; R < RW; ++R) yp += sp[Ly::s_wo + chan(R, h)] * hb[D - 1][R];
     const float y = yp + xor32(yp) + sp[Ly::s_bo];
 
-    // Upstream gradient of the ray sum.
+    // Upstream gradient of the ray sum (Eq. 3), or of the voxel loss (Eq. 2).
     float dA = 0.0f;
-    if (wave_valid) {
+    float dmu_vox = 0.0f;
+    if (vloss) {
+      const float mu = act_fwd(a.out_act, a.mu_max, y);
+      const float tgt = trilinear(a.vols + (size_t)tid * a.vol_n * a.vol_n * a.vol_n, a.vol_n, x);
+      const float res = mu - tgt;
+      dmu_vox = valid ? (float)((res > 0.0f) - (res < 0.0f)) * b.inv_R : 0.0f;
+      const float l = half_sum((h == 0 && valid) ? fabsf(res) : 0.0f);
+      if (lane == 0 && wave_valid) b.wave_loss[wave_id] = l;
+    } else if (wave_valid) {
       if (b.dA_in) {
         dA = b.dA_in[ray];
       } else {
@@ -407,7 +607,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
         }
       }
     }
-    const float dmu = (valid && rr.hit) ? dA * rr.delta : 0.0f;
+    const float dmu = vloss ? dmu_vox : ((valid && rr.hit) ? dA * rr.delta : 0.0f);
     const float dy = dmu * act_grad(a.out_act, a.mu_max, y);
 
     // Output unit.
@@ -430,35 +630,52 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
       if (lane == 0) atomicAdd(acc + Ly::g_bo, sdy);
     }
 
-    // Hidden layers, last to first.
+    // Hidden layers, last to first.  Weight gradients: per 32x32 block, the FP32 tile of the layer's
+    // output gradient gives the bias row sums; the outer product over the wave's 32 points runs on
+    // MFMA (FP32 tiles, or bf16 tiles overlaid on the consumed FP32 ones in the BF16 form).
     float gz[RC];
+    __bf16* tGb = reinterpret_cast<__bf16*>(tH);
+    __bf16* tHb = reinterpret_cast<__bf16*>(tG);
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
       float ga[RW];
 #pragma unroll
       for (int R = 0; R < RW; ++R) ga[R] = hb[k][R] > 0.0f ? g[R] : 0.0f;
+      constexpr int dummy = 0;
+      (void)dummy;
       const int Kk = Ly::K(k);
       const float* hin = (k == 0) ? z : hb[k > 0 ? k - 1 : 0];
 #pragma unroll
       for (int mb = 0; mb < W / 32; ++mb) {
         tile_put<RW>(tG, ga, mb, lane);
-        for (int nb = 0; nb < (Kk + 31) / 32; ++nb) {
-          if (k == 0) tile_put<RC>(tH, z, nb, lane);
-          else tile_put<RW>(tH, hin, nb, lane);
-          wave_lds_sync();
-          tile_outer_add(tG, tH, acc, Ly::gW(k), Kk, mb, nb, lane);
-          wave_lds_sync();
-        }
+        if constexpr (P == 1) tile_put_bf16<RW>(tGb, ga, mb, lane);
+        wave_lds_sync();
         tile_rowsum_add(tG, acc, Ly::gb(k) + 32 * mb, 32, lane);
         wave_lds_sync();
+#pragma unroll
+        for (int nb = 0; nb < (Kk + 31) / 32; ++nb) {
+          if constexpr (P == 0) {
+            if (k == 0) tile_put<RC>(tH, z, nb, lane);
+            else tile_put<RW>(tH, hin, nb, lane);
+          } else {
+            if (k == 0) tile_put_bf16<RC>(tHb, z, nb, lane);
+            else tile_put_bf16<RW>(tHb, hin, nb, lane);
+          }
+          wave_lds_sync();
+          if constexpr (P == 0) tile_outer_add(tG, tH, acc, Ly::gW(k), Kk, mb, nb, lane);
+          else tile_outer_add_bf16(tGb, tHb, acc, Ly::gW(k), Kk, mb, nb, lane);
+          wave_lds_sync();
+        }
       }
       if (k > 0) {
         float gp[RW];
-        layer_bwd_data<W, W>(sp + Ly::sW(k), ga, gp, lane);
+        if constexpr (P == 0) layer_bwd_data<W, W>(sp + Ly::sW(k), ga, gp, lane);
+        else layer_bwd_data_bf16<W, W>(reinterpret_cast<const bf16x8*>(sp) + Ly::wb(k), ga, gp, lane);
 #pragma unroll
         for (int R = 0; R < RW; ++R) g[R] = gp[R];
       } else {
-        layer_bwd_data<C, W>(sp + Ly::sW(0), ga, gz, lane);
+        if constexpr (P == 0) layer_bwd_data<C, W>(sp + Ly::sW(0), ga, gz, lane);
+        else layer_bwd_data_bf16<C, W>(reinterpret_cast<const bf16x8*>(sp) + Ly::wb(0), ga, gz, lane);
       }
     }
 
@@ -492,7 +709,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
       for (int r = 0; r < RC; ++r) gx[r] = gz[r];
     }
 
-    if (valid && dmu != 0.0f) scatter_half<L>(a.lt, b.grad_table, x, h, gx);
+    scatter_half<L>(a.lt, b.recs, cursor, x, h, gx, valid && (rr.hit || vloss), n, tbase);
   }
 
   __syncthreads();
@@ -623,9 +840,156 @@ __global__ void k_init(float* __restrict__ params, int64_t n_table, int64_t dens
   }
 }
 
+// Record offsets, step 1 (one block per bin): exclusive scan of the bin's per-block counts ->
+// offsets relative to the bin's first record; the bin's total.
+__global__ void __launch_bounds__(256) k_bin_rowscan(const uint32_t* __restrict__ counts, int grid,
+                                                     uint32_t* __restrict__ rel, uint32_t* __restrict__ totals) {
+  __shared__ uint32_t part[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int per = (grid + 255) / 256;
+  const int w0 = t * per, w1 = min(grid, w0 + per);
+  const uint32_t* row = counts + (size_t)b * grid;
+  uint32_t s = 0;
+  for (int w = w0; w < w1; ++w) s += row[w];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const uint32_t v = t >= o ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;
+  for (int w = w0; w < w1; ++w) {
+    rel[(size_t)b * grid + w] = run;
+    run += row[w];
+  }
+  if (t == 255) totals[b] = part[255];
+}
+
+// Record offsets, step 2 (one block): bin starts and the list of reduction pieces (bin, first record,
+// count, 1 if the bin is split over several pieces).
+__global__ void __launch_bounds__(1024) k_bin_pieces(const uint32_t* __restrict__ totals, int n_bins,
+                                                     uint32_t dense_end, uint32_t* __restrict__ bin_start,
+                                                     int4* __restrict__ pieces, int32_t* __restrict__ n_pieces) {
+  __shared__ uint32_t part_rec[1024], part_pc[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = (n_bins + nt - 1) / nt;
+  const int b0 = t * per, b1 = min(n_bins, b0 + per);
+  uint32_t srec = 0, spc = 0;
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t piece = kPiece;
+    srec += totals[b];
+    spc += (totals[b] + piece - 1) / piece;
+  }
+  part_rec[t] = srec;
+  part_pc[t] = spc;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {
+    const uint32_t ar = t >= o ? part_rec[t - o] : 0u, ap = t >= o ? part_pc[t - o] : 0u;
+    __syncthreads();
+    part_rec[t] += ar;
+    part_pc[t] += ap;
+    __syncthreads();
+  }
+  uint32_t rec = part_rec[t] - srec, pc = part_pc[t] - spc;
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t piece = kPiece;
+    const uint32_t tot = totals[b];
+    bin_start[b] = rec;
+    const uint32_t np = (tot + piece - 1) / piece;
+    for (uint32_t k = 0; k < np; ++k)
+      pieces[pc + k] = make_int4(b, (int)(rec + k * piece), (int)min(piece, tot - k * piece), np > 1 ? 1 : 0);
+    rec += tot;
+    pc += np;
+  }
+  if (t == nt - 1) *n_pieces = (int32_t)part_pc[t];
+}
+
+// Reduces each piece of records in a 2^kBinBits-entry LDS tile, then adds the tile into the table
+// gradient: a plain read-add-write when the piece is the bin's only one (the block owns those
+// entries), coalesced atomics otherwise.
+__global__ void __launch_bounds__(1024) k_bin_reduce(const BinRec* __restrict__ recs, const int4* __restrict__ pieces,
+                                                     const int32_t* __restrict__ n_pieces,
+                                                     float* __restrict__ grad_table, int64_t n_entries) {
+  extern __shared__ float tile[];
+  constexpr int NB = 1 << kBinBits;
+  const int np = *n_pieces;
+  for (int pc = blockIdx.x; pc < np; pc += gridDim.x) {
+    for (int e = threadIdx.x; e < 2 * NB; e += blockDim.x) tile[e] = 0.0f;
+    __syncthreads();
+    const int4 P = pieces[pc];
+    const uint32_t base = (uint32_t)P.x << kBinBits;
+    const BinRec* __restrict__ src = recs + (size_t)P.y;
+    constexpr int U = 8;       // records in flight per thread; lane-contiguous (coalesced) loads
+    for (int r0 = 0; r0 < P.z; r0 += blockDim.x * U) {
+      BinRec rc[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int r = r0 + k * blockDim.x + threadIdx.x;
+        if (r < P.z) rc[k] = src[r];
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int r = r0 + k * blockDim.x + threadIdx.x;
+        if (r < P.z) {
+          const uint32_t e = rc[k].idx - base;
+          atomicAdd(tile + 2 * e, rc[k].v0);
+          atomicAdd(tile + 2 * e + 1, rc[k].v1);
+        }
+      }
+    }
+    __syncthreads();
+    const int64_t lim = min((int64_t)NB, n_entries - (int64_t)base);
+    float2* g2 = reinterpret_cast<float2*>(grad_table) + base;
+    for (int e = threadIdx.x; e < lim; e += blockDim.x) {
+      const float2 v = make_float2(tile[2 * e], tile[2 * e + 1]);
+      if (P.w) {
+        if (v.x != 0.0f) atomicAdd(&g2[e].x, v.x);
+        if (v.y != 0.0f) atomicAdd(&g2[e].y, v.y);
+      } else {
+        float2 o = g2[e];
+        o.x += v.x;
+        o.y += v.y;
+        g2[e] = o;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Per-block FP64 sums of squared errors and maxima of gt (for PSNR): partials[2b] = sum,
+// partials[2b + 1] = max.
+__global__ void __launch_bounds__(256) k_sqerr(const float* __restrict__ gt, const float* __restrict__ pred,
+                                               int64_t n, double* __restrict__ partials) {
+  __shared__ double ss[256], sm[256];
+  double s = 0.0, mx = -1e300;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    const double d = (double)pred[q] - (double)gt[q];
+    s += d * d;
+    mx = fmax(mx, (double)gt[q]);
+  }
+  ss[threadIdx.x] = s;
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      ss[threadIdx.x] += ss[threadIdx.x + o];
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = ss[0];
+    partials[2 * blockIdx.x + 1] = sm[0];
+  }
+}
+
 // Raw encoding of n points (all levels, natural channel order) and optional corner entries.
-__global__ void k_encode(const LevelTab lt, const float2* __restrict__ table, const float* __restrict__ xn,
-                         int64_t n, float* __restrict__ enc, uint32_t* __restrict__ idx_out) {
+__global__ void k_encode(const LevelTab lt, const void* __restrict__ table, int half_table,
+                         const float* __restrict__ xn, int64_t n, float* __restrict__ enc,
+                         uint32_t* __restrict__ idx_out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n * lt.L) return;
   const int64_t p = q / lt.L;
@@ -636,7 +1000,8 @@ __global__ void k_encode(const LevelTab lt, const float2* __restrict__ table, co
   level_corners(lt.res[l], lt.off[l], lt.stride[l], lt.mask, x, idx, w);
   float s0 = 0.0f, s1 = 0.0f;
   for (int c = 0; c < 8; ++c) {
-    const float2 v = table[idx[c]];
+    const float2 v = half_table ? __half22float2(reinterpret_cast<const __half2*>(table)[idx[c]])
+                                : reinterpret_cast<const float2*>(table)[idx[c]];
     s0 += w[c] * v.x;
     s1 += w[c] * v.y;
   }
@@ -649,13 +1014,13 @@ __global__ void k_encode(const LevelTab lt, const float2* __restrict__ table, co
 // ---------------------------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------------------------
-template <int L, int W, int D>
+template <int L, int W, int D, int P>
 static KernelSet make_set() {
   constexpr int C = 2 * L;
-  using Ly = Lay<C, W, D>;
+  using Ly = Lay<C, W, D, P>;
   KernelSet ks;
-  ks.fwd = reinterpret_cast<const void*>(&k_fwd<L, W, D>);
-  ks.bwd = reinterpret_cast<const void*>(&k_bwd<L, W, D>);
+  ks.fwd = reinterpret_cast<const void*>(&k_fwd<L, W, D, P>);
+  ks.bwd = reinterpret_cast<const void*>(&k_bwd<L, W, D, P>);
   ks.fwd_lds = Ly::s_n * sizeof(float);
   const int nd_pad = (Ly::g_n + 3) & ~3;
   ks.bwd_lds = (Ly::s_n + nd_pad + kWavesPerBlock * 2 * 32 * kTile) * sizeof(float);
@@ -666,9 +1031,9 @@ static KernelSet make_set() {
 }
 
 KernelSet kernel_set(int L, int W, int D, int precision) {
-  if (precision != 0) return KernelSet{};
-#define NIC_CASE(l, w, d) \
-  if (L == l && W == w && D == d) return make_set<l, w, d>();
+#define NIC_CASE(l, w, d)                                      \
+  if (L == l && W == w && D == d)                              \
+    return precision ? make_set<l, w, d, 1>() : make_set<l, w, d, 0>();
   NIC_CASE(8, 32, 1) NIC_CASE(8, 32, 2) NIC_CASE(8, 32, 3) NIC_CASE(8, 32, 4)
   NIC_CASE(16, 32, 1) NIC_CASE(16, 32, 2) NIC_CASE(16, 32, 3) NIC_CASE(16, 32, 4)
   NIC_CASE(8, 64, 4) NIC_CASE(16, 64, 4)
@@ -676,16 +1041,18 @@ KernelSet kernel_set(int L, int W, int D, int precision) {
   return KernelSet{};
 }
 
-hipError_t launch_fwd(const KernelSet& ks, const FwdArgs& a, hipStream_t s) {
-  const int64_t blocks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
+hipError_t launch_fwd(const KernelSet& ks, const FwdArgs& a, int max_grid, size_t extra_lds, hipStream_t s) {
+  int64_t blocks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
   if (blocks == 0) return hipSuccess;
+  if (max_grid > 0 && blocks > max_grid) blocks = max_grid;
   void* args[] = {const_cast<FwdArgs*>(&a)};
-  return hipLaunchKernel(ks.fwd, dim3((unsigned)blocks), dim3(kBlock), args, ks.fwd_lds, s);
+  return hipLaunchKernel(ks.fwd, dim3((unsigned)blocks), dim3(kBlock), args, ks.fwd_lds + extra_lds, s);
 }
 
-hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, int grid, hipStream_t s) {
+hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, int grid, size_t extra_lds,
+                      hipStream_t s) {
   void* args[] = {const_cast<FwdArgs*>(&a), const_cast<BwdArgs*>(&b)};
-  return hipLaunchKernel(ks.bwd, dim3((unsigned)grid), dim3(kBlock), args, ks.bwd_lds, s);
+  return hipLaunchKernel(ks.bwd, dim3((unsigned)grid), dim3(kBlock), args, ks.bwd_lds + extra_lds, s);
 }
 
 hipError_t launch_rays(const RaysArgs& a, hipStream_t s) {
@@ -745,12 +1112,34 @@ hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const 
   return hipGetLastError();
 }
 
-hipError_t launch_encode(const LevelTab& lt, const float* table, const float* xn, int64_t n, float* enc,
-                         uint32_t* idx, hipStream_t s) {
+hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t dense_end, uint32_t* rel,
+                           uint32_t* totals, uint32_t* bin_start, int4* pieces, int32_t* n_pieces, hipStream_t s) {
+  k_bin_rowscan<<<n_bins, 256, 0, s>>>(counts, grid, rel, totals);
+  k_bin_pieces<<<1, 1024, 0, s>>>(totals, n_bins, dense_end, bin_start, pieces, n_pieces);
+  return hipGetLastError();
+}
+
+size_t bin_reduce_lds() { return (size_t)2 * (1 << kBinBits) * sizeof(float); }
+
+hipError_t launch_bin_reduce(const BinRec* recs, const int4* pieces, const int32_t* n_pieces, float* grad_table,
+                             int64_t n_entries, int grid, hipStream_t s) {
+  k_bin_reduce<<<grid, 1024, bin_reduce_lds(), s>>>(recs, pieces, n_pieces, grad_table, n_entries);
+  return hipGetLastError();
+}
+
+const void* bin_reduce_kernel() { return reinterpret_cast<const void*>(&k_bin_reduce); }
+
+hipError_t launch_sqerr(const float* gt, const float* pred, int64_t n, double* partials, int n_blocks,
+                        hipStream_t s) {
+  k_sqerr<<<n_blocks, 256, 0, s>>>(gt, pred, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(const LevelTab& lt, const void* table, int half_table, const float* xn, int64_t n,
+                         float* enc, uint32_t* idx, hipStream_t s) {
   const int64_t tot = n * lt.L;
   if (tot == 0) return hipSuccess;
-  k_encode<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(lt, reinterpret_cast<const float2*>(table), xn, n, enc,
-                                                         idx);
+  k_encode<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(lt, table, half_table, xn, n, enc, idx);
   return hipGetLastError();
 }
 

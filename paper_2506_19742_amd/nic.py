@@ -37,7 +37,7 @@ class nic_config(C.Structure):
                 ("base_res", C.c_int32), ("max_res", C.c_int32), ("mlp_depth", C.c_int32),
                 ("mlp_width", C.c_int32), ("out_act", C.c_int32), ("samples_per_ray", C.c_int32),
                 ("rays_per_step", C.c_int32), ("layernorm", C.c_int32), ("precision", C.c_int32),
-                ("mu_max", C.c_double), ("ln_eps", C.c_double), ("lr", C.c_double),
+                ("n_tables", C.c_int32), ("pad_", C.c_int32), ("mu_max", C.c_double), ("ln_eps", C.c_double), ("lr", C.c_double),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("adam_eps", C.c_double),
                 ("seed", C.c_uint64)]
 
@@ -57,7 +57,8 @@ EXPORTS = ["nic_describe", "nic_workspace_size", "nic_create", "nic_destroy", "n
            "nic_set_projections", "nic_tensors", "nic_sync_params", "nic_init_params", "nic_step",
            "nic_train", "nic_view_for_step", "nic_draw_rays", "nic_forward", "nic_backward",
            "nic_adam", "nic_zero_grad", "nic_query", "nic_render_volume", "nic_encode",
-           "nic_get_step", "nic_set_timing", "nic_kernel_times"]
+           "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step",
+           "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr"]
 
 _lib = None
 
@@ -94,6 +95,12 @@ def lib():
             "nic_get_step": ([vp], C.c_int64),
             "nic_set_timing": ([vp, C.c_int32], C.c_int32),
             "nic_kernel_times": ([vp, P(C.c_double), P(C.c_int64), P(C.c_int32)], C.c_int32),
+            "nic_voxel_step": ([vp, vp, C.c_int32, vp], C.c_int32),
+            "nic_voxel_train": ([vp, C.c_int32, C.c_int32, P(C.c_float)], C.c_int32),
+            "nic_set_volumes": ([vp, vp, C.c_int32], C.c_int32),
+            "nic_export_mlp": ([vp, vp, P(C.c_size_t)], C.c_int32),
+            "nic_import_mlp": ([vp, vp, C.c_size_t], C.c_int32),
+            "nic_psnr": ([vp, vp, vp, C.c_int64, P(C.c_double)], C.c_int32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -136,13 +143,14 @@ class Config:
     beta2: float = 0.999
     adam_eps: float = 1e-8
     seed: int = 0
+    n_tables: int = 1
 
     def c(self) -> nic_config:
         return nic_config(self.n_levels, self.feats_per_level, self.log2_table, self.base_res,
                           self.max_res, self.mlp_depth, self.mlp_width, self.out_act,
                           self.samples_per_ray, self.rays_per_step, self.layernorm, self.precision,
-                          self.mu_max, self.ln_eps, self.lr, self.beta1, self.beta2, self.adam_eps,
-                          self.seed)
+                          self.n_tables, 0, self.mu_max, self.ln_eps, self.lr, self.beta1,
+                          self.beta2, self.adam_eps, self.seed)
 
 
 def config_for(w, **over) -> Config:
@@ -303,7 +311,7 @@ class Model:
     def get_step(self) -> int:
         return int(lib().nic_get_step(self.h))
 
-    KERNEL_KINDS = ("rays", "forward", "backward", "reduce", "adam")
+    KERNEL_KINDS = ("rays", "forward", "backward", "reduce", "adam", "bin_scan", "bin_reduce")
 
     def set_timing(self, enable: bool):
         _check(lib().nic_set_timing(self.h, 1 if enable else 0))
@@ -315,6 +323,39 @@ class Model:
         cnt = C.c_int32()
         _check(lib().nic_kernel_times(self.h, ms, calls, C.byref(cnt)))
         return {self.KERNEL_KINDS[k]: (ms[k], int(calls[k])) for k in range(cnt.value)}
+
+    # --- Mapping Consistency Initialization -----------------------------------------------------
+    def set_volumes(self, vols):
+        """Pre-training targets: device float32 [n_tables][n][n][n]."""
+        self.vols = vols
+        _check(lib().nic_set_volumes(self.h, _ptr(vols), int(vols.shape[-1])))
+
+    def voxel_step(self, n_points: int, xn=None, loss=None):
+        _check(lib().nic_voxel_step(self.h, _ptr(xn), n_points, _ptr(loss)))
+
+    def voxel_train(self, n_steps: int, n_points: int, want_loss: bool = True):
+        if want_loss:
+            out = np.zeros(max(n_steps, 1), np.float32)
+            _check(lib().nic_voxel_train(self.h, n_steps, n_points, out.ctypes.data_as(C.POINTER(C.c_float))))
+            return out[:n_steps]
+        _check(lib().nic_voxel_train(self.h, n_steps, n_points, None))
+        return None
+
+    def export_mlp(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib().nic_export_mlp(self.h, None, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        _check(lib().nic_export_mlp(self.h, buf, C.byref(n)))
+        return bytes(buf)
+
+    def import_mlp(self, blob: bytes):
+        buf = (C.c_char * len(blob)).from_buffer_copy(blob)
+        _check(lib().nic_import_mlp(self.h, buf, len(blob)))
+
+    def psnr(self, gt, pred) -> float:
+        out = C.c_double()
+        _check(lib().nic_psnr(self.h, _ptr(gt), _ptr(pred), gt.numel(), C.byref(out)))
+        return float(out.value)
 
     # --- parameter helpers ------------------------------------------------------------------------
     def n_params(self):

@@ -333,3 +333,53 @@ def test_paper_scale_sampled_rays(ora):
     assert rel(g[:nt], og[:nt]) <= GRAD_TOL
     assert rel(g[nt:], og[nt:]) <= GRAD_TOL
     c.model.close()
+
+
+def test_autograd_function_matches_oracle_and_fd(ora, tiny):
+    """The hand-written backward behind torch.autograd.Function: Eq. (3) loss written in torch on
+    top of the rendered ray sums; gradient vs the oracle (1e-4) and vs FP32 central differences."""
+    from paper_2506_19742_amd import autograd as ag
+    c = tiny
+    p = random_params(ora, c.oc, 30, 0.1)
+    c.set_params(p)
+    pix, jit, tp, tj = _rays(c, 128, 31)
+    v = 4
+    params = ag.leaf_params(c.model)
+    params.grad = None
+    gt = torch.tensor(c.A[v].ravel()[pix], device="cuda")
+    A = ag.render(params, c.model, v, tp, tj)
+    loss = (A - gt).abs().mean()
+    loss.backward()
+    g = c.model.flat(params.grad)
+    ol, _, og = ora.ray_batch(c.oc, c.g, p, float(c.g.angles[v]), c.A[v], pix, jit)
+    nt = ora.n_params(c.oc)[1]
+    assert abs(loss.item() - ol) <= FWD_TOL * abs(ol)
+    assert rel(g[:nt], og[:nt]) <= GRAD_TOL
+    assert rel(g[nt:], og[nt:]) <= GRAD_TOL
+    # FP32 central differences of a smooth functional sum_r w_r A_r on the largest gradients
+    w = torch.tensor(np.random.default_rng(32).standard_normal(128), dtype=torch.float32, device="cuda")
+    params.grad = None
+    (ag.render(params, c.model, v, tp, tj) * w).sum().backward()
+    gw = params.grad.detach().clone()
+    nt_, nd_, do_ = c.model.n_params()
+    # finest level: an entry touches few samples, so the perturbation crosses few ReLU kinks
+    fine0 = 2 * c.model.layout["offset"][-1]
+    cand = torch.cat([fine0 + torch.topk(gw[fine0:nt_].abs(), 4).indices,
+                      do_ + torch.topk(gw[do_:do_ + nd_].abs(), 4).indices])
+    def central(k, h):
+        old = params[k].item()
+        params[k] = old + h
+        fp = float((c.model.forward(v, tp, tj).double() * w.double()).sum())
+        params[k] = old - h
+        fm = float((c.model.forward(v, tp, tj).double() * w.double()).sum())
+        params[k] = old
+        return (fp - fm) / (2 * h)
+
+    # Rays the perturbed entry does not touch give bit-identical sums in fp and fm, so their FP32
+    # rounding cancels; the remaining noise is a few 1e-6 of the touched rays' sums.
+    with torch.no_grad():
+        for k in cand.tolist():
+            h = 1e-3 * max(1.0, abs(params[k].item()))
+            fd = central(k, h)
+            assert abs(fd - gw[k].item()) <= 3e-2 * abs(gw[k].item()) + 2e-3, (k, fd, gw[k].item())
+    params.requires_grad_(False)

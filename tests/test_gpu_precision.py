@@ -1,0 +1,104 @@
+"""Precision form: BF16 MFMA operands with FP32 accumulation for the MLP, FP16 copy of the hash table
+for the gathers, FP32 master weights, gradients, LayerNorm statistics, ray sums, loss and Adam.
+
+The error of every result against the FP64 oracle is reported (printed and written to
+gpurun_out/precision_errors.json when that folder exists) and checked against bounds derived from
+the rounding units: FP16 entries carry 2^-11 relative error, so the encoding stays within ~1e-3 of its
+scale; BF16 operands (2^-8) through a 3-layer MLP put mu and the ray sums within a few 1e-2;
+gradients carry the BF16 error of every operand of the backward MFMAs.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2506_19742_amd import nic, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+BOUNDS = {"enc": 2e-3, "mu": 3e-2, "A_pred": 3e-2, "loss": 3e-2, "grad_table": 0.1, "grad_dense": 0.1,
+          "params_10_steps": 3e-2}
+
+
+def rel(gpu, ora):
+    gpu = np.asarray(gpu, np.float64)
+    ora = np.asarray(ora, np.float64)
+    d = np.abs(gpu - ora)
+    scale = np.abs(ora).max() or 1.0
+    return float(d.max() / scale), float(np.median(d) / scale)
+
+
+def test_precision_form_error_table(ora):
+    w = synth.WORKLOADS["tiny64_mixed"]
+    cfg = nic.config_for(w, seed=3)
+    assert cfg.precision == 1
+    ph, g, A = synth.scan(w)
+    oc = ora.Config(n_levels=cfg.n_levels, feats=2, log2_table=cfg.log2_table, base_res=cfg.base_res,
+                    max_res=cfg.max_res, depth=cfg.mlp_depth, width=cfg.mlp_width)
+    tot, nt, nd = ora.n_params(oc)
+    rng = np.random.default_rng(40)
+    p = synth.init_params(nt // 2, 2, ora.dense_layout(oc), oc.depth, 41).astype(np.float64)
+    p[:nt] = rng.standard_normal(nt) * 0.05
+    p = p.astype(np.float32).astype(np.float64)
+    print("[gpu] precision form: creating model", flush=True)
+    m = nic.Model(cfg, g)
+    m.set_projections(torch.tensor(A, device="cuda"))
+    m.load_params(p)
+    th = m.tensors()[4]
+    assert th is not None and th.numel() == nt
+    assert torch.equal(th.float(), m.tensors()[0][:nt].half().float())
+    out = {}
+
+    x = rng.random((4000, 3)).astype(np.float32)
+    tx = torch.tensor(x, device="cuda")
+    out["enc"] = rel(m.encode(tx).cpu().numpy(), ora.encode(oc, p[:nt], x))
+    out["mu"] = rel(m.query(tx).cpu().numpy(), ora.field(oc, p, x))
+
+    v = 6
+    pix, jit = synth.ray_batch(42, g.n_pix, cfg.rays_per_step, cfg.samples_per_ray)
+    tp, tj = torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda")
+    a = m.forward(v, tp, tj).cpu().numpy()
+    ol, oa, og = ora.ray_batch(oc, g, p, float(g.angles[v]), A[v], pix, jit)
+    out["A_pred"] = rel(a, oa)
+    res = oa - A[v].ravel()[pix]
+    dA = (np.sign(res) / len(pix)).astype(np.float32)
+    m.zero_grad()
+    m.backward(v, tp, tj, torch.tensor(dA, device="cuda"))
+    gr = m.flat(m.tensors()[1])
+    out["grad_table"] = rel(gr[:nt], og[:nt])
+    out["grad_dense"] = rel(gr[nt:], og[nt:])
+    loss = torch.zeros(1, device="cuda")
+
+    # ten full steps with explicit rays against the FP64 oracle's ten steps
+    m.load_params(p)
+    for t in m.tensors()[1:4]:
+        t.zero_()
+    op, om, ov = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    t0 = m.get_step()
+    losses = []
+    for k in range(10):
+        pix, jit = synth.ray_batch(50 + k, g.n_pix, cfg.rays_per_step, cfg.samples_per_ray)
+        vv = (7 * k + 1) % g.n_views
+        m.step(vv, torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda"), loss)
+        l_o, _, g_o = ora.ray_batch(oc, g, op, float(g.angles[vv]), A[vv], pix, jit)
+        ora.adam(op, g_o, om, ov, t0 + k + 1)
+        losses.append((loss.item(), l_o))
+    lg, lo = np.array(losses).T
+    out["loss"] = rel(lg, lo)
+    out["params_10_steps"] = rel(m.flat(m.tensors()[0]), op)
+    # Adam keeps the FP16 gather copy in step with the FP32 master table
+    assert torch.equal(th.float(), m.tensors()[0][:nt].half().float())
+    m.close()
+
+    print("precision form, error vs FP64 oracle (max / median, normalised by max |oracle|):")
+    for k, (mx, md) in out.items():
+        print(f"  {k:16s} {mx:.3e} / {md:.3e}   bound {BOUNDS[k]:.0e}")
+    od = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(od):
+        with open(os.path.join(od, "precision_errors.json"), "w") as f:
+            json.dump({k: {"max": v[0], "median": v[1], "bound": BOUNDS[k]} for k, v in out.items()}, f, indent=1)
+    for k, (mx, md) in out.items():
+        assert mx <= BOUNDS[k], (k, mx)

@@ -53,6 +53,16 @@ def test_ray_pixels_full_permutation(ora):
     assert sorted(pix.tolist()) == list(range(300))
 
 
+def test_voxel_points_are_philox_words(ora):
+    """Pre-training points: the first three words of Philox block (p, t, 0, 6), each as a 24-bit
+    uniform; checked against the published generator (pinned by its known answers above)."""
+    xn = ora.voxel_points(77, 5, 300)
+    for p in (0, 1, 299):
+        w = ora.philox([p, 5, 0, 6], [77, 0])
+        assert xn[p].tolist() == [float(int(x) >> 8) / 2 ** 24 for x in w[:3]]
+    assert xn.min() >= 0 and xn.max() < 1 and abs(xn.mean() - 0.5) < 0.05
+
+
 def test_view_order_visits_every_view_each_epoch(ora):
     V = 50
     for e in range(3):
