@@ -178,7 +178,7 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
   p.o_counts = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_offs = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_pieces = take(p.max_pieces * 16);
-  p.o_npieces = take(4);
+  p.o_npieces = take(8);
   p.o_recs = take(max_recs * (int64_t)sizeof(BinRec));
   p.o_sqerr = take(2 * kSqerrBlocks * 8);
   p.bytes = o;
@@ -207,6 +207,7 @@ struct nic_model {
   uint32_t *counts = nullptr, *offs = nullptr, *totals = nullptr, *bin_start = nullptr;
   int4* pieces = nullptr;
   int32_t* n_pieces = nullptr;
+  uint32_t* rec_max = nullptr;
   BinRec* recs = nullptr;
   int reduce_grid = 0;
   double* sqerr = nullptr;
@@ -334,7 +335,7 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   {
     KTimer kt(m, 5);
     NIC_HIP(launch_bin_scan(m->counts, pl.n_bins, grid, pl.dense_end, m->offs, m->totals, m->bin_start, m->pieces,
-                            m->n_pieces, m->stream));
+                            m->n_pieces, m->rec_max, m->stream));
   }
   b.enc_in = m->enc;
   b.a_pred_out = m->apred;
@@ -343,14 +344,15 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   b.bin_offsets = m->offs;
   b.bin_start = m->bin_start;
   b.recs = m->recs;
+  b.rec_max_bits = m->rec_max;
   {
     KTimer kt(m, 2);
     NIC_HIP(launch_bwd(pl.ks, a, b, grid, bin_lds, m->stream));
   }
   {
     KTimer kt(m, 6);
-    NIC_HIP(launch_bin_reduce(m->recs, m->pieces, m->n_pieces, m->grads, pl.n_entries * pl.n_tables,
-                              m->reduce_grid, m->stream));
+    NIC_HIP(launch_bin_reduce(m->recs, m->pieces, m->n_pieces, m->totals, m->rec_max, m->grads,
+                              pl.n_entries * pl.n_tables, m->reduce_grid, m->stream));
   }
   KTimer kt(m, 3);
   NIC_HIP(launch_reduce(m->partials, grid, pl.nd_pad, (int)pl.n_dense, m->grads + pl.dense_off, loss_src, loss_n,
@@ -506,6 +508,7 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   m->offs = (uint32_t*)(ws + p.o_offs);
   m->pieces = (int4*)(ws + p.o_pieces);
   m->n_pieces = (int32_t*)(ws + p.o_npieces);
+  m->rec_max = (uint32_t*)(ws + p.o_npieces + 4);
   m->recs = (BinRec*)(ws + p.o_recs);
   m->totals = (uint32_t*)(ws + p.o_totals);
   m->bin_start = (uint32_t*)(ws + p.o_binstart);

@@ -15,7 +15,7 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kPtsPerBlock = kPtsPerWave * kWavesPerBlock;
 constexpr int kTile = 33;            // padded row length of the per-wave LDS transpose tiles
-constexpr int kBinBits = 13;         // table-gradient bins of 2^13 entries (64 KB of FP32 x 2 in LDS)
+constexpr int kBinBits = 12;         // table-gradient bins of 2^12 entries (64 KB of int64 x 2 in LDS)
 constexpr int kPiece = 1 << 16;      // records reduced by one block in one pass
 
 // One corner contribution to the table gradient: entry and the two feature gradients.

@@ -53,6 +53,7 @@ struct BwdArgs {
   const uint32_t* bin_start;    // [n_bins] first record of each bin
   BinRec* recs;          // table-gradient records grouped by bin
   float* wave_loss;      // voxel-loss mode: per-wave sum of |mu - target|
+  uint32_t* rec_max_bits;  // bit pattern of the largest |record| of the step (atomic max)
 };
 
 struct RaysArgs {
@@ -106,9 +107,11 @@ hipError_t launch_to_half(const float* src, __half* dst, int64_t n, int n_cu, hi
 hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const InitArgs& ia, int n_cu,
                        hipStream_t s);
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t dense_end, uint32_t* rel,
-                           uint32_t* totals, uint32_t* bin_start, int4* pieces, int32_t* n_pieces, hipStream_t s);
-hipError_t launch_bin_reduce(const BinRec* recs, const int4* pieces, const int32_t* n_pieces, float* grad_table,
-                             int64_t n_entries, int grid, hipStream_t s);
+                           uint32_t* totals, uint32_t* bin_start, int4* pieces, int32_t* n_pieces,
+                           uint32_t* rec_max_bits, hipStream_t s);
+hipError_t launch_bin_reduce(const BinRec* recs, const int4* pieces, const int32_t* n_pieces, const uint32_t* totals,
+                             const uint32_t* rec_max_bits, float* grad_table, int64_t n_entries, int grid,
+                             hipStream_t s);
 size_t bin_reduce_lds();
 const void* bin_reduce_kernel();
 hipError_t launch_sqerr(const float* gt, const float* pred, int64_t n, double* partials, int n_blocks,

@@ -155,7 +155,7 @@ __device__ __forceinline__ void encode_half(const LevelTab& T, const void* __res
 template <int L>
 __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restrict__ recs, uint32_t* cursor,
                                              const float x[3], int h, const float gx[L], bool active, int ln,
-                                             uint32_t tbase) {
+                                             uint32_t tbase, float& vmax) {
 #pragma unroll
   for (int j = 0; j < L / 4; ++j) {
 #pragma unroll
@@ -199,6 +199,7 @@ __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restri
       if (active && tail) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
+          vmax = fmaxf(vmax, fmaxf(fabsf(v0[c]), fabsf(v1[c])));
           const uint32_t slot = atomicAdd(cursor + (idx[c] >> kBinBits), 1u);
           BinRec r;
           r.idx = idx[c];
@@ -346,9 +347,8 @@ __device__ __forceinline__ void tile_put_bf16(__bf16* tile, const float* v, int 
   }
 }
 
-// BF16 form of tile_outer_add: K = 32 points in two steps of 16.
-__device__ __forceinline__ void tile_outer_add_bf16(const __bf16* tG, const __bf16* tH, float* acc, int wbase,
-                                                    int K, int mb, int nb, int lane) {
+// BF16 form of tile_outer: K = 32 points in two steps of 16.
+__device__ __forceinline__ f32x16 tile_outer_bf16(const __bf16* tG, const __bf16* tH, int lane) {
   const int m = lane & 31, h = lane >> 5;
   f32x16 d = f32x16{};
 #pragma unroll
@@ -357,11 +357,7 @@ __device__ __forceinline__ void tile_outer_add_bf16(const __bf16* tG, const __bf
     const bf16x8 bb = *reinterpret_cast<const bf16x8*>(tH + m * kTile16 + 16 * s + 8 * h);
     d = mfma32_bf16(a, bb, d);
   }
-  const int col = 32 * nb + m;
-  if (col < K) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) atomicAdd(acc + wbase + (32 * mb + chan(r, h)) * K + col, d[r]);
-  }
+  return d;
 }
 
 // Writes rows [32*blk, 32*blk + 32) of a per-point vector (n registers, layout chan) into a
@@ -376,30 +372,72 @@ __device__ __forceinline__ void tile_put(float* tile, const float* v, int blk, i
   }
 }
 
-// acc_lds[base + m] += sum over the 32 points of tile row m, for m < nrows.
-__device__ __forceinline__ void tile_rowsum_add(const float* tile, float* acc, int base, int nrows, int lane) {
+// Sum over the 32 points of tile row m = lane % 32 (valid in every lane).
+__device__ __forceinline__ float tile_rowsum(const float* tile, int lane) {
   const int m = lane & 31, h = lane >> 5;
   float s = 0.0f;
 #pragma unroll
   for (int j = 0; j < 16; ++j) s += tile[m * kTile + 16 * h + j];
-  s += xor32(s);
-  if (h == 0 && m < nrows) atomicAdd(acc + base + m, s);
+  return s + xor32(s);
 }
 
-// acc_lds[wbase + (32 mb + row) * K + 32 nb + col] += (G^T H) over the wave's 32 points, with
-// tiles tG = G rows [32mb, 32mb+32), tH = H rows [32nb, 32nb+32).
-__device__ __forceinline__ void tile_outer_add(const float* tG, const float* tH, float* acc, int wbase,
-                                               int K, int mb, int nb, int lane) {
+// G^T H over the wave's 32 points for tiles tG = G rows [32mb, 32mb+32), tH = H rows [32nb, ..):
+// register r of lane (m, h) = entry (32mb + chan(r, h), 32nb + m).
+__device__ __forceinline__ f32x16 tile_outer(const float* tG, const float* tH, int lane) {
   const int m = lane & 31, h = lane >> 5;
   f32x16 d = f32x16{};
 #pragma unroll
   for (int s = 0; s < 16; ++s) d = mfma32(tG[m * kTile + 16 * h + s], tH[m * kTile + 16 * h + s], d);
-  const int col = 32 * nb + m;
-  if (col < K) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) atomicAdd(acc + wbase + (32 * mb + chan(r, h)) * K + col, d[r]);
-  }
+  return d;
 }
+
+// Cross-wave combination of the dense-gradient contributions of one chunk without float atomics
+// (LDS float atomics are slow on gfx950): every wave stages its values in its own LDS slot, then
+// each wave adds a disjoint quarter of the entries, summed over the four slots, to the block's
+// accumulator.  Must be reached by all waves of the block.
+struct Combine {
+  float* slot0;        // slot of wave 0; wave w's slot is slot0 + w * stride
+  int stride;
+  int wv, lane;
+  __device__ float* mine() const { return slot0 + wv * stride; }
+  __device__ float sum4(int q) const {
+    return slot0[q] + slot0[stride + q] + slot0[2 * stride + q] + slot0[3 * stride + q];
+  }
+  // dW block (mb, nb) of a layer with K inputs at acc[wbase]; optional 32 row sums (bias) staged
+  // after the tile are added at acc[bbase + 32 mb + m] when bbase >= 0.
+  __device__ void tile(float* acc, const f32x16& d, int wbase, int K, int mb, int nb, float brow, int bbase) const {
+    float* S = mine();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) S[r * kWave + lane] = d[r];
+    if (lane < 32) S[1024 + lane] = brow;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int q = 256 * wv + 64 * k + lane;
+      const int r = q >> 6, l2 = q & 63, m2 = l2 & 31, h2 = l2 >> 5;
+      const int col = 32 * nb + m2;
+      if (col < K) acc[wbase + (32 * mb + chan(r, h2)) * K + col] += sum4(q);
+    }
+    if (bbase >= 0 && wv == 1 && lane < 32) acc[bbase + 32 * mb + lane] += sum4(1024 + lane);
+    __syncthreads();
+  }
+  // Up to two vectors of 32 row sums (a at abase + m, b at bbase + m for m < nrows) and one scalar.
+  __device__ void rows(float* acc, float a, int abase, float b, int bbase, int nrows, float sc, int scbase) const {
+    float* S = mine();
+    if (lane < 32) {
+      S[lane] = a;
+      S[32 + lane] = b;
+    }
+    if (lane == 0) S[64] = sc;
+    __syncthreads();
+    if (wv == 0 && lane < nrows) {
+      if (abase >= 0) acc[abase + lane] += sum4(lane);
+      if (bbase >= 0) acc[bbase + lane] += sum4(32 + lane);
+    }
+    if (wv == 0 && lane == 0 && scbase >= 0) acc[scbase] += sum4(64);
+    __syncthreads();
+  }
+};
 
 __device__ __forceinline__ float act_fwd(int act, float mu_max, float y) {
   if (act == 1) return y;
@@ -551,6 +589,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
 
   const int waves_per_ray = a.N / kPtsPerWave;
   const int64_t n_chunks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
+  float vmax = 0.0f;
   for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
     const int64_t wave_id = chunk * kWavesPerBlock + wv;
     const int64_t p = wave_id * kPtsPerWave + n;
@@ -618,16 +657,15 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
       g[R] = dy * sp[Ly::s_wo + chan(R, h)];
       t[R] = dy * hb[D - 1][R];
     }
+    const Combine cmb{acc + nd_pad, 2 * 32 * kTile, wv, lane};
+    const float sdy = half_sum(h == 0 ? dy : 0.0f);
 #pragma unroll
     for (int mb = 0; mb < W / 32; ++mb) {
       tile_put<RW>(tG, t, mb, lane);
       wave_lds_sync();
-      tile_rowsum_add(tG, acc, Ly::g_wo + 32 * mb, 32, lane);
+      const float rs = tile_rowsum(tG, lane);
       wave_lds_sync();
-    }
-    {
-      const float sdy = half_sum(h == 0 ? dy : 0.0f);
-      if (lane == 0) atomicAdd(acc + Ly::g_bo, sdy);
+      cmb.rows(acc, rs, Ly::g_wo + 32 * mb, 0.0f, -1, 32, sdy, mb == 0 ? Ly::g_bo : -1);
     }
 
     // Hidden layers, last to first.  Weight gradients: per 32x32 block, the FP32 tile of the layer's
@@ -650,21 +688,26 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
         tile_put<RW>(tG, ga, mb, lane);
         if constexpr (P == 1) tile_put_bf16<RW>(tGb, ga, mb, lane);
         wave_lds_sync();
-        tile_rowsum_add(tG, acc, Ly::gb(k) + 32 * mb, 32, lane);
+        const float brow = tile_rowsum(tG, lane);
         wave_lds_sync();
 #pragma unroll
         for (int nb = 0; nb < (Kk + 31) / 32; ++nb) {
+          f32x16 d;
           if constexpr (P == 0) {
             if (k == 0) tile_put<RC>(tH, z, nb, lane);
             else tile_put<RW>(tH, hin, nb, lane);
+            wave_lds_sync();
+            d = tile_outer(tG, tH, lane);
           } else {
             if (k == 0) tile_put_bf16<RC>(tHb, z, nb, lane);
             else tile_put_bf16<RW>(tHb, hin, nb, lane);
+            wave_lds_sync();
+            d = tile_outer_bf16(tGb, tHb, lane);
           }
           wave_lds_sync();
-          if constexpr (P == 0) tile_outer_add(tG, tH, acc, Ly::gW(k), Kk, mb, nb, lane);
-          else tile_outer_add_bf16(tGb, tHb, acc, Ly::gW(k), Kk, mb, nb, lane);
-          wave_lds_sync();
+          // stage in the slot whose tile is no longer needed: tH (FP32 form) / tG (BF16 form)
+          const Combine c2{P == 0 ? acc + nd_pad + 32 * kTile : acc + nd_pad, 2 * 32 * kTile, wv, lane};
+          c2.tile(acc, d, Ly::gW(k), Kk, mb, nb, brow, nb == 0 ? Ly::gb(k) : -1);
         }
       }
       if (k > 0) {
@@ -695,9 +738,9 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
       tile_put<RC>(tG, t1, 0, lane);
       tile_put<RC>(tH, t2, 0, lane);
       wave_lds_sync();
-      tile_rowsum_add(tG, acc, Ly::g_lng, C, lane);
-      tile_rowsum_add(tH, acc, Ly::g_lnb, C, lane);
+      const float rg = tile_rowsum(tG, lane), rb = tile_rowsum(tH, lane);
       wave_lds_sync();
+      cmb.rows(acc, rg, Ly::g_lng, rb, Ly::g_lnb, C, 0.0f, -1);
       sg += xor32(sg);
       sgx += xor32(sgx);
       const float mg = sg * (1.0f / C), mgx = sgx * (1.0f / C);
@@ -709,8 +752,12 @@ __global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b
       for (int r = 0; r < RC; ++r) gx[r] = gz[r];
     }
 
-    scatter_half<L>(a.lt, b.recs, cursor, x, h, gx, valid && (rr.hit || vloss), n, tbase);
+    scatter_half<L>(a.lt, b.recs, cursor, x, h, gx, valid && (rr.hit || vloss), n, tbase, vmax);
   }
+  // Largest |record| of the step (positive floats order like their bit patterns): sets the
+  // fixed-point scale of the bin reduction.
+  for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
+  if (lane == 0) atomicMax(b.rec_max_bits, __float_as_uint(vmax));
 
   __syncthreads();
   for (int e2 = threadIdx.x; e2 < nd_pad; e2 += blockDim.x)
@@ -871,7 +918,9 @@ __global__ void __launch_bounds__(256) k_bin_rowscan(const uint32_t* __restrict_
 // count, 1 if the bin is split over several pieces).
 __global__ void __launch_bounds__(1024) k_bin_pieces(const uint32_t* __restrict__ totals, int n_bins,
                                                      uint32_t dense_end, uint32_t* __restrict__ bin_start,
-                                                     int4* __restrict__ pieces, int32_t* __restrict__ n_pieces) {
+                                                     int4* __restrict__ pieces, int32_t* __restrict__ n_pieces,
+                                                     uint32_t* __restrict__ rec_max_bits) {
+  if (threadIdx.x == 0) *rec_max_bits = 0u;
   __shared__ uint32_t part_rec[1024], part_pc[1024];
   const int t = threadIdx.x, nt = blockDim.x;
   const int per = (n_bins + nt - 1) / nt;
@@ -908,18 +957,30 @@ __global__ void __launch_bounds__(1024) k_bin_pieces(const uint32_t* __restrict_
 
 // Reduces each piece of records in a 2^kBinBits-entry LDS tile, then adds the tile into the table
 // gradient: a plain read-add-write when the piece is the bin's only one (the block owns those
-// entries), coalesced atomics otherwise.
+// entries), coalesced atomics otherwise.  The tile accumulates in int64 fixed point (LDS integer
+// atomics are an order of magnitude faster than LDS float atomics on gfx950, and integer sums are
+// exact, so the result does not depend on record order).  Scale 2^e per bin: with c records in the
+// bin and every |record| <= vmax, |sum| <= c vmax < 2^61 2^-e, so nothing overflows; each record is
+// rounded once to a multiple of 2^-e (error <= 2^-e-1 = c vmax 2^-63).
 __global__ void __launch_bounds__(1024) k_bin_reduce(const BinRec* __restrict__ recs, const int4* __restrict__ pieces,
                                                      const int32_t* __restrict__ n_pieces,
+                                                     const uint32_t* __restrict__ totals,
+                                                     const uint32_t* __restrict__ rec_max_bits,
                                                      float* __restrict__ grad_table, int64_t n_entries) {
-  extern __shared__ float tile[];
+  extern __shared__ unsigned long long tile64[];
   constexpr int NB = 1 << kBinBits;
   const int np = *n_pieces;
+  const float vmax = __uint_as_float(*rec_max_bits);
   for (int pc = blockIdx.x; pc < np; pc += gridDim.x) {
-    for (int e = threadIdx.x; e < 2 * NB; e += blockDim.x) tile[e] = 0.0f;
+    for (int e = threadIdx.x; e < 2 * NB; e += blockDim.x) tile64[e] = 0ull;
     __syncthreads();
     const int4 P = pieces[pc];
     const uint32_t base = (uint32_t)P.x << kBinBits;
+    int ev, ec;
+    frexpf(vmax, &ev);                                  // vmax < 2^ev
+    frexpf((float)totals[P.x] + 1.0f, &ec);             // count < 2^ec
+    const int e = 61 - ev - ec;
+    const double up = ldexp(1.0, e), down = ldexp(1.0, -e);
     const BinRec* __restrict__ src = recs + (size_t)P.y;
     constexpr int U = 8;       // records in flight per thread; lane-contiguous (coalesced) loads
     for (int r0 = 0; r0 < P.z; r0 += blockDim.x * U) {
@@ -933,25 +994,26 @@ __global__ void __launch_bounds__(1024) k_bin_reduce(const BinRec* __restrict__ 
       for (int k = 0; k < U; ++k) {
         const int r = r0 + k * blockDim.x + threadIdx.x;
         if (r < P.z) {
-          const uint32_t e = rc[k].idx - base;
-          atomicAdd(tile + 2 * e, rc[k].v0);
-          atomicAdd(tile + 2 * e + 1, rc[k].v1);
+          const uint32_t q = rc[k].idx - base;
+          atomicAdd(tile64 + 2 * q, (unsigned long long)__double2ll_rn((double)rc[k].v0 * up));
+          atomicAdd(tile64 + 2 * q + 1, (unsigned long long)__double2ll_rn((double)rc[k].v1 * up));
         }
       }
     }
     __syncthreads();
     const int64_t lim = min((int64_t)NB, n_entries - (int64_t)base);
     float2* g2 = reinterpret_cast<float2*>(grad_table) + base;
-    for (int e = threadIdx.x; e < lim; e += blockDim.x) {
-      const float2 v = make_float2(tile[2 * e], tile[2 * e + 1]);
+    for (int q = threadIdx.x; q < lim; q += blockDim.x) {
+      const float2 v = make_float2((float)((double)(long long)tile64[2 * q] * down),
+                                   (float)((double)(long long)tile64[2 * q + 1] * down));
       if (P.w) {
-        if (v.x != 0.0f) atomicAdd(&g2[e].x, v.x);
-        if (v.y != 0.0f) atomicAdd(&g2[e].y, v.y);
+        if (v.x != 0.0f) atomicAdd(&g2[q].x, v.x);
+        if (v.y != 0.0f) atomicAdd(&g2[q].y, v.y);
       } else {
-        float2 o = g2[e];
+        float2 o = g2[q];
         o.x += v.x;
         o.y += v.y;
-        g2[e] = o;
+        g2[q] = o;
       }
     }
     __syncthreads();
@@ -1113,17 +1175,20 @@ hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const 
 }
 
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t dense_end, uint32_t* rel,
-                           uint32_t* totals, uint32_t* bin_start, int4* pieces, int32_t* n_pieces, hipStream_t s) {
+                           uint32_t* totals, uint32_t* bin_start, int4* pieces, int32_t* n_pieces,
+                           uint32_t* rec_max_bits, hipStream_t s) {
   k_bin_rowscan<<<n_bins, 256, 0, s>>>(counts, grid, rel, totals);
-  k_bin_pieces<<<1, 1024, 0, s>>>(totals, n_bins, dense_end, bin_start, pieces, n_pieces);
+  k_bin_pieces<<<1, 1024, 0, s>>>(totals, n_bins, dense_end, bin_start, pieces, n_pieces, rec_max_bits);
   return hipGetLastError();
 }
 
-size_t bin_reduce_lds() { return (size_t)2 * (1 << kBinBits) * sizeof(float); }
+size_t bin_reduce_lds() { return (size_t)2 * (1 << kBinBits) * sizeof(unsigned long long); }
 
-hipError_t launch_bin_reduce(const BinRec* recs, const int4* pieces, const int32_t* n_pieces, float* grad_table,
-                             int64_t n_entries, int grid, hipStream_t s) {
-  k_bin_reduce<<<grid, 1024, bin_reduce_lds(), s>>>(recs, pieces, n_pieces, grad_table, n_entries);
+hipError_t launch_bin_reduce(const BinRec* recs, const int4* pieces, const int32_t* n_pieces, const uint32_t* totals,
+                             const uint32_t* rec_max_bits, float* grad_table, int64_t n_entries, int grid,
+                             hipStream_t s) {
+  k_bin_reduce<<<grid, 1024, bin_reduce_lds(), s>>>(recs, pieces, n_pieces, totals, rec_max_bits, grad_table,
+                                                    n_entries);
   return hipGetLastError();
 }
 
