@@ -27,6 +27,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "train pts/s (fwd+bwd); secs to 30 dB PSNR, BF16+MCI vs plain FP32"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+COPY_BYTES = 256 << 20
+
+
+def kernel_source_sha() -> str:
+    """Hash of the HIP sources: measured traffic is used only for the kernels it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2506_19742_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, precision: int):
+    """HBM bytes per launch of `kernel` from profiles/traffic.json (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE passes scaled by the same counters on a plain copy of known size), or None when the
+    file is absent, covers another workload, or was taken on other kernel sources."""
+    try:
+        import json as _json
+        t = _json.load(open(TRAFFIC_JSON))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != kernel_source_sha():
+        return None
+    rec = t.get("workloads", {}).get(f"{workload}:p{precision}", {}).get(kernel)
+    return None if rec is None else rec.get("bytes_per_launch")
 
 
 def algorithmic_bytes(cfg, lay, n_points):
@@ -78,7 +106,20 @@ def main():
     ap.add_argument("--workload", default="ct256")
     ap.add_argument("--precision", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--render", type=int, default=0,
+                    help="also time forward-only inference of the full n^3 volume (voxel centres)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build measures "
               "the single-GPU training step; multi-GPU sharding is design-only.", file=sys.stderr)
@@ -146,9 +187,22 @@ def main():
         "kernels": per_kernel,
         "final_loss": float(losses[-1]),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, w.name, cfg.precision),
                      "algorithmic_bytes_per_launch": ab[dom]},
     }
+    if args.render:
+        n = args.render
+        vol = model.render_volume(n, n, n)          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            vol = model.render_volume(n, n, n)
+        torch.cuda.synchronize()
+        rs = (time.perf_counter() - t0) / reps
+        out["render"] = {"n": n, "points": n ** 3, "seconds": rs, "pts_per_s": n ** 3 / rs}
+        del vol
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, g, A)

@@ -220,6 +220,15 @@ nic_status nic_set_volumes(nic_model* m, const float* vols_dev, int32_t n);
 nic_status nic_export_mlp(nic_model* m, void* buf, size_t* bytes);
 nic_status nic_import_mlp(nic_model* m, const void* buf, size_t bytes);
 
+/* Checkpoint and resume: the full training state (parameters, Adam moments, step counter; the
+ * device draws are counter-based, so the step and the seed define the rest) as a host blob with a
+ * header naming the configuration.  nic_save_state with buf == NULL stores the size in *bytes.
+ * nic_load_state requires the same configuration and seed (NIC_EVERSION otherwise), zeroes the
+ * gradients and refreshes the FP16 table copy.  A resumed run reproduces an uninterrupted one bit
+ * for bit.  Both synchronise the stream. */
+nic_status nic_save_state(nic_model* m, void* buf, size_t* bytes);
+nic_status nic_load_state(nic_model* m, const void* buf, size_t bytes);
+
 /* PSNR = 10 log10(max(gt)^2 / mean((pred - gt)^2)) over n voxels (device float32 arrays); the
  * squared errors are summed in FP64 on the device; synchronous.  +inf when pred == gt. */
 nic_status nic_psnr(nic_model* m, const float* gt_dev, const float* pred_dev, int64_t n, double* psnr_host);

@@ -50,6 +50,19 @@ struct MlpBlobHeader {
   double mu_max, ln_eps;
 };
 constexpr uint32_t kBlobVersion = 1;
+
+// Training-state blob: this header, then params, adam_m, adam_v (FP32, n_params_padded each).
+struct StateHeader {
+  char magic[4];
+  uint32_t version;
+  int32_t cfg_ints[13];   // levels, feats, log2_table, base_res, max_res, depth, width, out_act,
+                          // samples, rays, layernorm, precision, n_tables
+  int32_t pad_;
+  uint64_t seed;
+  int64_t n_params_pad;
+  int64_t step;
+};
+constexpr uint32_t kStateVersion = 1;
 constexpr int kKinds = 7;   // timed kernel kinds: rays, forward, backward, reduce, adam, bin scan, bin reduce
 
 int64_t up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -834,6 +847,64 @@ nic_status nic_import_mlp(nic_model* m, const void* buf, size_t bytes) {
   NIC_HIP(launch_fill(m->m + m->plan.dense_off, m->plan.n_dense, 0.0f, m->n_cu, m->stream));
   NIC_HIP(launch_fill(m->v + m->plan.dense_off, m->plan.n_dense, 0.0f, m->n_cu, m->stream));
   NIC_HIP(hipStreamSynchronize(m->stream));
+  return NIC_OK;
+}
+
+static void state_header(const nic_model* m, StateHeader& h) {
+  memset(&h, 0, sizeof h);
+  memcpy(h.magic, "NICS", 4);
+  h.version = kStateVersion;
+  const nic_config& c = m->cfg;
+  const int32_t v[13] = {c.n_levels, c.feats_per_level, c.log2_table, c.base_res, c.max_res, c.mlp_depth,
+                         c.mlp_width, c.out_act, c.samples_per_ray, c.rays_per_step, c.layernorm, c.precision,
+                         m->plan.n_tables};
+  memcpy(h.cfg_ints, v, sizeof v);
+  h.seed = c.seed;
+  h.n_params_pad = m->plan.n_params_pad;
+  h.step = m->step;
+}
+
+nic_status nic_save_state(nic_model* m, void* buf, size_t* bytes) {
+  if (!model_ok(m) || !bytes) return fail(NIC_EINVAL, "NULL argument");
+  const size_t n = (size_t)m->plan.n_params_pad * 4;
+  const size_t need = sizeof(StateHeader) + 3 * n;
+  if (!buf) {
+    *bytes = need;
+    return NIC_OK;
+  }
+  if (*bytes < need) return fail(NIC_EINVAL, "buffer too small (%zu < %zu)", *bytes, need);
+  StateHeader h;
+  state_header(m, h);
+  memcpy(buf, &h, sizeof h);
+  char* dst = (char*)buf + sizeof h;
+  NIC_HIP(hipMemcpyAsync(dst, m->params, n, hipMemcpyDeviceToHost, m->stream));
+  NIC_HIP(hipMemcpyAsync(dst + n, m->m, n, hipMemcpyDeviceToHost, m->stream));
+  NIC_HIP(hipMemcpyAsync(dst + 2 * n, m->v, n, hipMemcpyDeviceToHost, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  *bytes = need;
+  return NIC_OK;
+}
+
+nic_status nic_load_state(nic_model* m, const void* buf, size_t bytes) {
+  if (!model_ok(m) || !buf) return fail(NIC_EINVAL, "NULL argument");
+  if (bytes < sizeof(StateHeader)) return fail(NIC_EVERSION, "state blob too short");
+  StateHeader h, mine;
+  memcpy(&h, buf, sizeof h);
+  state_header(m, mine);
+  if (memcmp(h.magic, "NICS", 4) || h.version != kStateVersion) return fail(NIC_EVERSION, "not a state blob");
+  if (memcmp(h.cfg_ints, mine.cfg_ints, sizeof h.cfg_ints) || h.seed != mine.seed ||
+      h.n_params_pad != mine.n_params_pad)
+    return fail(NIC_EVERSION, "state of another configuration");
+  const size_t n = (size_t)m->plan.n_params_pad * 4;
+  if (bytes < sizeof h + 3 * n) return fail(NIC_EVERSION, "state blob truncated");
+  const char* src = (const char*)buf + sizeof h;
+  NIC_HIP(hipMemcpyAsync(m->params, src, n, hipMemcpyHostToDevice, m->stream));
+  NIC_HIP(hipMemcpyAsync(m->m, src + n, n, hipMemcpyHostToDevice, m->stream));
+  NIC_HIP(hipMemcpyAsync(m->v, src + 2 * n, n, hipMemcpyHostToDevice, m->stream));
+  NIC_HIP(launch_fill(m->grads, m->plan.n_params_pad, 0.0f, m->n_cu, m->stream));
+  if (m->th) NIC_HIP(launch_to_half(m->params, m->th, m->plan.n_table, m->n_cu, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  m->step = h.step;
   return NIC_OK;
 }
 

@@ -16,7 +16,10 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kPtsPerBlock = kPtsPerWave * kWavesPerBlock;
 constexpr int kTile = 33;            // padded row length of the per-wave LDS transpose tiles
 constexpr int kBinBits = 12;         // table-gradient bins of 2^12 entries (64 KB of int64 x 2 in LDS)
-constexpr int kPiece = 1 << 16;      // records reduced by one block in one pass
+// Records reduced by one block in one pass.  A bin is split over several blocks only beyond this
+// size; below it every bin is reduced by one block, which makes the table gradient exactly
+// reproducible (integer sums, no float atomics).
+constexpr int kPiece = 1 << 22;
 
 // One corner contribution to the table gradient: entry and the two feature gradients.
 struct BinRec {

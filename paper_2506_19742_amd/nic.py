@@ -58,7 +58,8 @@ EXPORTS = ["nic_describe", "nic_workspace_size", "nic_create", "nic_destroy", "n
            "nic_train", "nic_view_for_step", "nic_draw_rays", "nic_forward", "nic_backward",
            "nic_adam", "nic_zero_grad", "nic_query", "nic_render_volume", "nic_encode",
            "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step",
-           "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr"]
+           "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr",
+           "nic_save_state", "nic_load_state"]
 
 _lib = None
 
@@ -101,6 +102,8 @@ def lib():
             "nic_export_mlp": ([vp, vp, P(C.c_size_t)], C.c_int32),
             "nic_import_mlp": ([vp, vp, C.c_size_t], C.c_int32),
             "nic_psnr": ([vp, vp, vp, C.c_int64, P(C.c_double)], C.c_int32),
+            "nic_save_state": ([vp, vp, P(C.c_size_t)], C.c_int32),
+            "nic_load_state": ([vp, vp, C.c_size_t], C.c_int32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -351,6 +354,17 @@ class Model:
     def import_mlp(self, blob: bytes):
         buf = (C.c_char * len(blob)).from_buffer_copy(blob)
         _check(lib().nic_import_mlp(self.h, buf, len(blob)))
+
+    def save_state(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib().nic_save_state(self.h, None, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        _check(lib().nic_save_state(self.h, buf, C.byref(n)))
+        return bytes(buf)
+
+    def load_state(self, blob: bytes):
+        buf = (C.c_char * len(blob)).from_buffer_copy(blob)
+        _check(lib().nic_load_state(self.h, buf, len(blob)))
 
     def psnr(self, gt, pred) -> float:
         out = C.c_double()

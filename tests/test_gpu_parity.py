@@ -383,3 +383,46 @@ def test_autograd_function_matches_oracle_and_fd(ora, tiny):
             fd = central(k, h)
             assert abs(fd - gw[k].item()) <= 3e-2 * abs(gw[k].item()) + 2e-3, (k, fd, gw[k].item())
     params.requires_grad_(False)
+
+
+def test_repeated_steps_are_bitwise_reproducible(ora):
+    """The whole step is deterministic (integer table-gradient sums, fixed-order dense reductions)."""
+    w = synth.WORKLOADS["tiny64"]
+    ph, g, A = synth.scan(w)
+    outs = []
+    for _ in range(2):
+        m = nic.Model(nic.config_for(w, seed=13), g)
+        m.set_projections(torch.tensor(A, device="cuda"))
+        m.train(5, want_loss=False)
+        outs.append(m.tensors()[0].clone())
+        m.close()
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_checkpoint_resume_is_bitwise(ora):
+    """Kill/resume: 3 steps, save, load into a fresh model, 3 more steps == 6 uninterrupted steps."""
+    w = synth.WORKLOADS["tiny64"]
+    ph, g, A = synth.scan(w)
+    proj = torch.tensor(A, device="cuda")
+    ref = nic.Model(nic.config_for(w, seed=21), g)
+    ref.set_projections(proj)
+    ref_losses = ref.train(6)
+    a = nic.Model(nic.config_for(w, seed=21), g)
+    a.set_projections(proj)
+    a.train(3)
+    blob = a.save_state()
+    a.close()
+    b = nic.Model(nic.config_for(w, seed=21), g)
+    b.set_projections(proj)
+    b.init_params(999)                       # different state before loading
+    b.load_state(blob)
+    assert b.get_step() == 3
+    losses = b.train(3)
+    assert torch.equal(b.tensors()[0], ref.tensors()[0])
+    assert np.array_equal(losses, ref_losses[3:])
+    c = nic.Model(nic.config_for(w, seed=22), g)
+    with pytest.raises(nic.NicError) as ei:
+        c.load_state(blob)
+    assert ei.value.status == nic.NIC_EVERSION
+    for mm in (ref, b, c):
+        mm.close()
