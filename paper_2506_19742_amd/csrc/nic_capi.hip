@@ -180,7 +180,16 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
   p.o_absres = take(R * 4);
   p.o_loss = take(kLossHist * 4);
   p.o_pix = take(R * 4);
-  p.n_bins = (int)((p.n_entries * p.n_tables + (1 << kBinBits) - 1) >> kBinBits);
+  // Widest bins that keep the per-bin histogram (k_fwd) and cursors (k_bwd) in LDS beside their tiles.
+  {
+    const int64_t ent = p.n_entries * p.n_tables;
+    const int64_t room = (int64_t)kLdsBytes - (int64_t)std::max(p.ks.fwd_lds, p.ks.bwd_lds);
+    int sh = kBinBits;
+    while (sh < 31 && ((ent + (1ll << sh) - 1) >> sh) * 4 > room) ++sh;
+    if (room <= 0 || ((ent + (1ll << sh) - 1) >> sh) * 4 > room) { err = "gradient bins do not fit in LDS"; return false; }
+    p.lt.bin_shift = sh;
+    p.n_bins = (int)((ent + (1ll << sh) - 1) >> sh);
+  }
   const int64_t max_recs = R * N * L * 8;
   p.max_pieces = p.n_bins + max_recs / kPiece + 1;
   p.dense_end = 0;
@@ -365,7 +374,7 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   {
     KTimer kt(m, 6);
     NIC_HIP(launch_bin_reduce(m->recs, m->pieces, m->n_pieces, m->totals, m->rec_max, m->grads,
-                              pl.n_entries * pl.n_tables, m->reduce_grid, m->stream));
+                              pl.n_entries * pl.n_tables, pl.lt.bin_shift, m->reduce_grid, m->stream));
   }
   KTimer kt(m, 3);
   NIC_HIP(launch_reduce(m->partials, grid, pl.nd_pad, (int)pl.n_dense, m->grads + pl.dense_off, loss_src, loss_n,
@@ -424,6 +433,8 @@ nic_status nic_describe(const nic_config* cfg, nic_layout* out) {
   out->n_dense = p.n_dense;
   out->dense_offset = p.dense_off;
   out->n_params_padded = p.n_params_pad;
+  out->bin_shift = p.lt.bin_shift;
+  out->n_bins = p.n_bins;
   return NIC_OK;
 }
 

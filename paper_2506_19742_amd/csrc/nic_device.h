@@ -15,7 +15,11 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kPtsPerBlock = kPtsPerWave * kWavesPerBlock;
 constexpr int kTile = 33;            // padded row length of the per-wave LDS transpose tiles
-constexpr int kBinBits = 12;         // table-gradient bins of 2^12 entries (64 KB of int64 x 2 in LDS)
+constexpr int kBinBits = 12;         // reduction tile: 2^12 entries (64 KB of int64 x 2 in LDS)
+// A table-gradient bin spans 2^bin_shift entries, bin_shift >= kBinBits, chosen per model so that
+// the per-bin histogram fits in LDS beside the kernels' own tiles; a bin of more than one tile is
+// reduced tile by tile.
+constexpr int kLdsBytes = 160 * 1024;
 // Records reduced by one block in one pass.  A bin is split over several blocks only beyond this
 // size; below it every bin is reduced by one block, which makes the table gradient exactly
 // reproducible (integer sums, no float atomics).
@@ -207,6 +211,7 @@ struct LevelTab {
   uint32_t stride[kMaxLevels];   // N_l + 1 for a dense level, 0 for a hashed level
   uint32_t mask;                 // T - 1
   int32_t L;
+  int32_t bin_shift;             // log2 of the entries per table-gradient bin
 };
 
 // Cell g = min(floor(fl32(x * N)), N - 1) and fraction f = x*N - g (exact) along one axis.

@@ -110,8 +110,8 @@ hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_
                            uint32_t* totals, uint32_t* bin_start, int4* pieces, int32_t* n_pieces,
                            uint32_t* rec_max_bits, hipStream_t s);
 hipError_t launch_bin_reduce(const BinRec* recs, const int4* pieces, const int32_t* n_pieces, const uint32_t* totals,
-                             const uint32_t* rec_max_bits, float* grad_table, int64_t n_entries, int grid,
-                             hipStream_t s);
+                             const uint32_t* rec_max_bits, float* grad_table, int64_t n_entries, int bin_shift,
+                             int grid, hipStream_t s);
 size_t bin_reduce_lds();
 const void* bin_reduce_kernel();
 hipError_t launch_sqerr(const float* gt, const float* pred, int64_t n, double* partials, int n_blocks,

@@ -141,7 +141,7 @@ __device__ __forceinline__ void encode_half(const LevelTab& T, const void* __res
         run_flags(g0, g1, g2, ln, cont, tail);
         if (tail && hist) {
 #pragma unroll
-          for (int c = 0; c < 8; ++c) atomicAdd(hist + (idx[c] >> kBinBits), 1u);
+          for (int c = 0; c < 8; ++c) atomicAdd(hist + (idx[c] >> T.bin_shift), 1u);
         }
       }
     }
@@ -200,7 +200,7 @@ __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restri
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
           vmax = fmaxf(vmax, fmaxf(fabsf(v0[c]), fabsf(v1[c])));
-          const uint32_t slot = atomicAdd(cursor + (idx[c] >> kBinBits), 1u);
+          const uint32_t slot = atomicAdd(cursor + (idx[c] >> T.bin_shift), 1u);
           BinRec r;
           r.idx = idx[c];
           r.v0 = v0[c];
@@ -955,9 +955,10 @@ __global__ void __launch_bounds__(1024) k_bin_pieces(const uint32_t* __restrict_
   if (t == nt - 1) *n_pieces = (int32_t)part_pc[t];
 }
 
-// Reduces each piece of records in a 2^kBinBits-entry LDS tile, then adds the tile into the table
-// gradient: a plain read-add-write when the piece is the bin's only one (the block owns those
-// entries), coalesced atomics otherwise.  The tile accumulates in int64 fixed point (LDS integer
+// Reduces each piece of records in a 2^kBinBits-entry LDS tile (one pass over the piece per tile
+// when a bin spans several tiles), then adds the tile into the table gradient: a plain
+// read-add-write when the piece is the bin's only one (the block owns those entries), coalesced
+// atomics otherwise.  The tile accumulates in int64 fixed point (LDS integer
 // atomics are an order of magnitude faster than LDS float atomics on gfx950, and integer sums are
 // exact, so the result does not depend on record order).  Scale 2^e per bin: with c records in the
 // bin and every |record| <= vmax, |sum| <= c vmax < 2^61 2^-e, so nothing overflows; each record is
@@ -966,16 +967,19 @@ __global__ void __launch_bounds__(1024) k_bin_reduce(const BinRec* __restrict__ 
                                                      const int32_t* __restrict__ n_pieces,
                                                      const uint32_t* __restrict__ totals,
                                                      const uint32_t* __restrict__ rec_max_bits,
-                                                     float* __restrict__ grad_table, int64_t n_entries) {
+                                                     float* __restrict__ grad_table, int64_t n_entries,
+                                                     int bin_shift) {
   extern __shared__ unsigned long long tile64[];
   constexpr int NB = 1 << kBinBits;
   const int np = *n_pieces;
   const float vmax = __uint_as_float(*rec_max_bits);
-  for (int pc = blockIdx.x; pc < np; pc += gridDim.x) {
+  const int n_sub = 1 << (bin_shift - kBinBits);
+  for (int job = blockIdx.x; job < np * n_sub; job += gridDim.x) {
+    const int pc = job / n_sub, sub = job - pc * n_sub;
     for (int e = threadIdx.x; e < 2 * NB; e += blockDim.x) tile64[e] = 0ull;
     __syncthreads();
     const int4 P = pieces[pc];
-    const uint32_t base = (uint32_t)P.x << kBinBits;
+    const uint32_t base = ((uint32_t)P.x << bin_shift) + ((uint32_t)sub << kBinBits);
     int ev, ec;
     frexpf(vmax, &ev);                                  // vmax < 2^ev
     frexpf((float)totals[P.x] + 1.0f, &ec);             // count < 2^ec
@@ -993,8 +997,8 @@ __global__ void __launch_bounds__(1024) k_bin_reduce(const BinRec* __restrict__ 
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const int r = r0 + k * blockDim.x + threadIdx.x;
-        if (r < P.z) {
-          const uint32_t q = rc[k].idx - base;
+        const uint32_t q = rc[k].idx - base;   // wraps above NB for records of another tile
+        if (r < P.z && q < (uint32_t)NB) {
           atomicAdd(tile64 + 2 * q, (unsigned long long)__double2ll_rn((double)rc[k].v0 * up));
           atomicAdd(tile64 + 2 * q + 1, (unsigned long long)__double2ll_rn((double)rc[k].v1 * up));
         }
@@ -1006,7 +1010,7 @@ __global__ void __launch_bounds__(1024) k_bin_reduce(const BinRec* __restrict__ 
     for (int q = threadIdx.x; q < lim; q += blockDim.x) {
       const float2 v = make_float2((float)((double)(long long)tile64[2 * q] * down),
                                    (float)((double)(long long)tile64[2 * q + 1] * down));
-      if (P.w) {
+      if (P.w) {   // the bin is split over several pieces: other blocks add to the same entries
         if (v.x != 0.0f) atomicAdd(&g2[q].x, v.x);
         if (v.y != 0.0f) atomicAdd(&g2[q].y, v.y);
       } else {
@@ -1185,10 +1189,11 @@ hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_
 size_t bin_reduce_lds() { return (size_t)2 * (1 << kBinBits) * sizeof(unsigned long long); }
 
 hipError_t launch_bin_reduce(const BinRec* recs, const int4* pieces, const int32_t* n_pieces, const uint32_t* totals,
-                             const uint32_t* rec_max_bits, float* grad_table, int64_t n_entries, int grid,
-                             hipStream_t s) {
+                             const uint32_t* rec_max_bits, float* grad_table, int64_t n_entries, int bin_shift,
+                             int grid, hipStream_t s) {
+  if (bin_shift < kBinBits || bin_shift > 31) return hipErrorInvalidValue;
   k_bin_reduce<<<grid, 1024, bin_reduce_lds(), s>>>(recs, pieces, n_pieces, totals, rec_max_bits, grad_table,
-                                                    n_entries);
+                                                    n_entries, bin_shift);
   return hipGetLastError();
 }
 

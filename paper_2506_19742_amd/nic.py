@@ -45,7 +45,8 @@ class nic_config(C.Structure):
 class nic_layout(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("res", C.c_int32 * 16), ("dense", C.c_int32 * 16),
                 ("offset", C.c_int64 * 16), ("n_entries", C.c_int64), ("n_table", C.c_int64),
-                ("n_dense", C.c_int64), ("dense_offset", C.c_int64), ("n_params_padded", C.c_int64)]
+                ("n_dense", C.c_int64), ("dense_offset", C.c_int64), ("n_params_padded", C.c_int64),
+                ("bin_shift", C.c_int32), ("n_bins", C.c_int32)]
 
 
 class nic_tensor(C.Structure):
@@ -182,7 +183,7 @@ def nic_describe(cfg: Config) -> dict:
     return dict(res=list(out.res[:L]), dense=[bool(x) for x in out.dense[:L]],
                 offset=list(out.offset[:L]), n_entries=out.n_entries, n_table=out.n_table,
                 n_dense=out.n_dense, dense_offset=out.dense_offset,
-                n_params_padded=out.n_params_padded)
+                n_params_padded=out.n_params_padded, bin_shift=out.bin_shift, n_bins=out.n_bins)
 
 
 def nic_workspace_size(cfg: Config, geom) -> int:

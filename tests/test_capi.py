@@ -52,6 +52,23 @@ def test_paper_scale_sizes():
     assert lay["n_table"] + lay["n_dense"] == 12202171
 
 
+@pytest.mark.parametrize("width", [32, 64])
+def test_gradient_bins_cover_all_tables(width):
+    """Bins widen (2^bin_shift entries) as tables are added so the per-bin histogram stays in LDS."""
+    w = synth.WORKLOADS["ct256"]
+    prev = 0
+    for K in (1, 2, 4, 8, 16, 32):
+        lay = nic.nic_describe(nic.config_for(w, n_tables=K, mlp_width=width))
+        ent = lay["n_entries"] * K
+        assert lay["bin_shift"] >= 12 and lay["bin_shift"] >= prev
+        assert lay["n_bins"] == -(-ent // (1 << lay["bin_shift"]))
+        assert lay["n_bins"] * 4 <= 160 * 1024
+        if lay["bin_shift"] > 12:   # the narrower bins would not have fitted beside the kernels' tiles
+            assert -(-ent // (1 << (lay["bin_shift"] - 1))) > lay["n_bins"]
+        prev = lay["bin_shift"]
+    assert nic.nic_describe(nic.config_for(w, n_tables=1))["bin_shift"] == 12
+
+
 def test_workspace_size_and_validation():
     g = synth.cone_geometry(64, 50)
     cfg = nic.config_for(synth.WORKLOADS["tiny64"])

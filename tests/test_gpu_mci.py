@@ -77,6 +77,46 @@ def test_voxel_step_matches_oracle(ora):
     m.close()
 
 
+def test_voxel_step_wide_bins_matches_oracle(ora):
+    """Four 256^3-workload tables at width 64: bins of 2^14 entries, each reduced over 4 LDS tiles."""
+    K = 4
+    w = synth.WORKLOADS["ct256"]
+    cfg = nic.config_for(w, n_tables=K, mlp_width=64, seed=11)
+    lay = nic.nic_describe(cfg)
+    assert lay["bin_shift"] > 12
+    oc = ora.Config(n_levels=cfg.n_levels, feats=2, log2_table=cfg.log2_table, base_res=cfg.base_res,
+                    max_res=cfg.max_res, depth=cfg.mlp_depth, width=cfg.mlp_width)
+    print(f"[case] K={K} W=64 bin_shift={lay['bin_shift']} creating model", flush=True)
+    m = nic.Model(cfg, synth.cone_geometry(64, 4))
+    tot, nt1, nd = ora.n_params(oc)
+    rng = np.random.default_rng(70)
+    table = (rng.standard_normal(K * nt1) * 0.05).astype(np.float32).astype(np.float64)
+    dense = ora.init_params(oc, 71)[nt1:].astype(np.float32).astype(np.float64)
+    p = np.concatenate([table, dense])
+    m.load_params(p)
+    vols = _smooth_volumes(K, 24, 72)
+    m.set_volumes(torch.tensor(vols, device="cuda"))
+    B = 32 * K * 16
+    x = rng.random((B, 3)).astype(np.float32)
+    tid = np.arange(B) // (B // K)
+    loss = torch.zeros(1, device="cuda")
+    for t in m.tensors()[1:4]:
+        t.zero_()
+    m.voxel_step(B, torch.tensor(x, device="cuda"), loss)
+    ol, _, og = ora.voxel_batch(oc, p, vols, x, tid)
+    op, om, ov = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    ora.adam(op, og, om, ov, 1)
+    assert abs(loss.item() - ol) <= FWD_TOL * ol
+    got = m.flat(m.tensors()[0])
+    assert rel(got[:K * nt1], op[:K * nt1]) <= GRAD_TOL
+    assert rel(got[K * nt1:], op[K * nt1:]) <= GRAD_TOL
+    # every touched entry moved, every untouched entry stayed
+    touched = og[:K * nt1] != 0
+    assert np.array_equal(got[:K * nt1][~touched], p[:K * nt1][~touched])
+    assert np.mean(got[:K * nt1][touched] != p[:K * nt1][touched]) > 0.999
+    m.close()
+
+
 def test_voxel_train_with_device_points_matches_oracle(ora):
     """Points drawn on the device from Philox against the oracle's own draw."""
     K = 2
