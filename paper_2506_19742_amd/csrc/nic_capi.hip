@@ -79,10 +79,9 @@ struct Plan {
   KernelSet ks;
   // workspace offsets (bytes)
   int64_t o_params, o_grads, o_m, o_v, o_th, o_part, o_rays, o_wsum, o_enc, o_apred, o_absres, o_loss, o_pix;
-  int64_t o_counts, o_offs, o_pieces, o_npieces, o_recs, o_totals, o_binstart;
-  uint32_t dense_end = 0;
+  int64_t o_counts, o_offs, o_pieces, o_npieces, o_recs, o_totals, o_binstart, o_split, o_split_cnt;
   int n_bins = 0;
-  int64_t max_pieces = 0;
+  int64_t max_pieces = 0, max_split = 0;
   int64_t bytes = 0;
 };
 
@@ -192,16 +191,18 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
   }
   const int64_t max_recs = R * N * L * 8;
   p.max_pieces = p.n_bins + max_recs / kPiece + 1;
-  p.dense_end = 0;
-  for (int l = 0; l < L; ++l)
-    if (p.dense[l]) p.dense_end = (uint32_t)(p.off[l] + ((int64_t)p.res[l] + 1) * (p.res[l] + 1) * (p.res[l] + 1));
+  // bins cut into several pieces hold more than kPiece records each
+  p.max_split = std::min<int64_t>(p.n_bins, max_recs / (kPiece + 1) + 1);
+  const int64_t n_sub = 1ll << (p.lt.bin_shift - kBinBits);
   p.o_totals = take((int64_t)p.n_bins * 4);
   p.o_binstart = take((int64_t)p.n_bins * 4);
   p.o_counts = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_offs = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_pieces = take(p.max_pieces * 16);
-  p.o_npieces = take(8);
+  p.o_npieces = take(8);   // pieces, step's largest |record|
   p.o_recs = take(max_recs * (int64_t)sizeof(BinRec));
+  p.o_split = take(p.max_split * n_sub * (2ll << kBinBits) * 8);
+  p.o_split_cnt = take(p.max_split * n_sub * 4);
   p.o_sqerr = take(2 * kSqerrBlocks * 8);
   p.bytes = o;
   return true;
@@ -231,6 +232,8 @@ struct nic_model {
   int32_t* n_pieces = nullptr;
   uint32_t* rec_max = nullptr;
   BinRec* recs = nullptr;
+  unsigned long long* split_acc = nullptr;
+  uint32_t* split_cnt = nullptr;
   int reduce_grid = 0;
   double* sqerr = nullptr;
   const float* vols = nullptr;
@@ -356,8 +359,8 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   }
   {
     KTimer kt(m, 5);
-    NIC_HIP(launch_bin_scan(m->counts, pl.n_bins, grid, pl.dense_end, m->offs, m->totals, m->bin_start, m->pieces,
-                            m->n_pieces, m->rec_max, m->stream));
+    NIC_HIP(launch_bin_scan(m->counts, pl.n_bins, grid, m->offs, m->totals, m->bin_start, m->pieces, m->n_pieces,
+                            m->rec_max, m->stream));
   }
   b.enc_in = m->enc;
   b.a_pred_out = m->apred;
@@ -373,8 +376,19 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   }
   {
     KTimer kt(m, 6);
-    NIC_HIP(launch_bin_reduce(m->recs, m->pieces, m->n_pieces, m->totals, m->rec_max, m->grads,
-                              pl.n_entries * pl.n_tables, pl.lt.bin_shift, m->reduce_grid, m->stream));
+    BinReduceArgs br{};
+    br.recs = m->recs;
+    br.pieces = m->pieces;
+    br.n_pieces = m->n_pieces;
+    br.totals = m->totals;
+    br.rec_max_bits = m->rec_max;
+    br.grad_table = m->grads;
+    br.n_entries = pl.n_entries * pl.n_tables;
+    br.bin_shift = pl.lt.bin_shift;
+    br.n_sub = 1 << (pl.lt.bin_shift - kBinBits);
+    br.split_acc = m->split_acc;
+    br.split_cnt = m->split_cnt;
+    NIC_HIP(launch_bin_reduce(br, m->reduce_grid, m->stream));
   }
   KTimer kt(m, 3);
   NIC_HIP(launch_reduce(m->partials, grid, pl.nd_pad, (int)pl.n_dense, m->grads + pl.dense_off, loss_src, loss_n,
@@ -534,11 +548,19 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   m->n_pieces = (int32_t*)(ws + p.o_npieces);
   m->rec_max = (uint32_t*)(ws + p.o_npieces + 4);
   m->recs = (BinRec*)(ws + p.o_recs);
+  m->split_acc = (unsigned long long*)(ws + p.o_split);
+  m->split_cnt = (uint32_t*)(ws + p.o_split_cnt);
   m->totals = (uint32_t*)(ws + p.o_totals);
   m->bin_start = (uint32_t*)(ws + p.o_binstart);
   m->sqerr = (double*)(ws + p.o_sqerr);
   *out = m;
-  const nic_status st = nic_init_params(m, cfg->seed);
+  // split-bin accumulators and counters start at zero; every step leaves them at zero
+  nic_status st = NIC_OK;
+  if (launch_fill((float*)m->split_acc, (p.o_split_cnt - p.o_split) / 4, 0.0f, m->n_cu, m->stream) != hipSuccess ||
+      launch_fill((float*)m->split_cnt, p.max_split * (1ll << (p.lt.bin_shift - kBinBits)), 0.0f, m->n_cu,
+                  m->stream) != hipSuccess)
+    st = fail(NIC_EHIP, "workspace clear: %s", hipGetErrorString(hipGetLastError()));
+  if (st == NIC_OK) st = nic_init_params(m, cfg->seed);
   if (st != NIC_OK) {
     delete m;
     *out = nullptr;

@@ -106,12 +106,23 @@ hipError_t launch_fill(float* x, int64_t n, float val, int n_cu, hipStream_t s);
 hipError_t launch_to_half(const float* src, __half* dst, int64_t n, int n_cu, hipStream_t s);
 hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const InitArgs& ia, int n_cu,
                        hipStream_t s);
-hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t dense_end, uint32_t* rel,
-                           uint32_t* totals, uint32_t* bin_start, int4* pieces, int32_t* n_pieces,
-                           uint32_t* rec_max_bits, hipStream_t s);
-hipError_t launch_bin_reduce(const BinRec* recs, const int4* pieces, const int32_t* n_pieces, const uint32_t* totals,
-                             const uint32_t* rec_max_bits, float* grad_table, int64_t n_entries, int bin_shift,
-                             int grid, hipStream_t s);
+hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
+                           uint32_t* bin_start, int4* pieces, int32_t* n_pieces, uint32_t* rec_max_bits,
+                           hipStream_t s);
+struct BinReduceArgs {
+  const BinRec* recs;             // records grouped by bin
+  const int4* pieces;             // (bin, first record, count, split slot + 1 or 0)
+  const int32_t* n_pieces;
+  const uint32_t* totals;         // records per bin
+  const uint32_t* rec_max_bits;   // largest |record| of the step (float bits)
+  float* grad_table;              // FP32 table gradient, [n_entries][2]
+  int64_t n_entries;
+  int32_t bin_shift;              // log2 entries per bin
+  int32_t n_sub;                  // 2^(bin_shift - kBinBits) LDS tiles per bin
+  unsigned long long* split_acc;  // [slot][n_sub][2 << kBinBits] int64 accumulators of split bins, zero between steps
+  uint32_t* split_cnt;            // [slot][n_sub] pieces finished, zero between steps
+};
+hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s);
 size_t bin_reduce_lds();
 const void* bin_reduce_kernel();
 hipError_t launch_sqerr(const float* gt, const float* pred, int64_t n, double* partials, int n_blocks,

@@ -500,7 +500,7 @@ __device__ __forceinline__ void mlp_forward(const float* sp, const float* z, flo
 // Forward kernel
 // ---------------------------------------------------------------------------------------------
 template <int L, int W, int D, int P>
-__global__ void __launch_bounds__(kBlock) k_fwd(const FwdArgs a) {
+__global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_fwd(const FwdArgs a) {
   constexpr int C = 2 * L, RC = C / 2, RW = W / 2;
   using Ly = Lay<C, W, D, P>;
   extern __shared__ float smem[];
@@ -569,7 +569,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd(const FwdArgs a) {
 // Backward kernel (persistent over 128-point chunks)
 // ---------------------------------------------------------------------------------------------
 template <int L, int W, int D, int P>
-__global__ void __launch_bounds__(kBlock) k_bwd(const FwdArgs a, const BwdArgs b) {
+__global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a, const BwdArgs b) {
   constexpr int C = 2 * L, RC = C / 2, RW = W / 2;
   using Ly = Lay<C, W, D, P>;
   extern __shared__ float smem[];
@@ -796,26 +796,41 @@ __global__ void k_raysum(const float* __restrict__ wave_sum, int waves_per_ray, 
   a_pred[r] = A;
 }
 
-// grad_dense[k] += sum_g partials[g][k]; block 0 also forms loss = sum_r absres[r] * inv_R.
-__global__ void k_reduce(const float* __restrict__ partials, int n_blocks, int nd_pad, int nd,
-                         float* __restrict__ grad_dense, const float* __restrict__ absres, int n_rays,
-                         float inv_R, float* __restrict__ loss_out) {
-  __shared__ float red[256];
+// grad_dense[k] += sum_g partials[g][k] (fixed order: 16 strided groups, then the groups in order);
+// block 0 also forms loss = sum_r absres[r] * inv_R.
+__global__ void __launch_bounds__(1024) k_reduce(const float* __restrict__ partials, int n_blocks, int nd_pad,
+                                                 int nd, float* __restrict__ grad_dense,
+                                                 const float* __restrict__ absres, int n_rays, float inv_R,
+                                                 float* __restrict__ loss_out) {
+  __shared__ float red[1024];
   const int k = blockIdx.x * 64 + (threadIdx.x & 63);
   const int grp = threadIdx.x >> 6;
-  float s = 0.0f;
-  if (k < nd)
-    for (int gi = grp; gi < n_blocks; gi += 4) s += partials[(size_t)gi * nd_pad + k];
-  red[threadIdx.x] = s;
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+  if (k < nd) {
+    int gi = grp;
+    for (; gi + 48 < n_blocks; gi += 64) {
+      s0 += partials[(size_t)gi * nd_pad + k];
+      s1 += partials[(size_t)(gi + 16) * nd_pad + k];
+      s2 += partials[(size_t)(gi + 32) * nd_pad + k];
+      s3 += partials[(size_t)(gi + 48) * nd_pad + k];
+    }
+    for (; gi < n_blocks; gi += 16) s0 += partials[(size_t)gi * nd_pad + k];
+  }
+  red[threadIdx.x] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  if (grp == 0 && k < nd) grad_dense[k] += red[threadIdx.x] + red[threadIdx.x + 64] + red[threadIdx.x + 128] + red[threadIdx.x + 192];
+  if (grp == 0 && k < nd) {
+    float t = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += red[threadIdx.x + 64 * q];
+    grad_dense[k] += t;
+  }
   if (blockIdx.x == 0 && loss_out) {
     __syncthreads();
     float l = 0.0f;
     for (int r = threadIdx.x; r < n_rays; r += blockDim.x) l += absres[r];
     red[threadIdx.x] = l;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = 512; o > 0; o >>= 1) {
       if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
       __syncthreads();
     }
@@ -914,41 +929,45 @@ __global__ void __launch_bounds__(256) k_bin_rowscan(const uint32_t* __restrict_
   if (t == 255) totals[b] = part[255];
 }
 
-// Record offsets, step 2 (one block): bin starts and the list of reduction pieces (bin, first record,
-// count, 1 if the bin is split over several pieces).
+// Record offsets, step 2 (one block): bin starts and the list of reduction pieces (bin, first
+// record, count, split slot + 1 for a bin cut into several pieces, else 0).
 __global__ void __launch_bounds__(1024) k_bin_pieces(const uint32_t* __restrict__ totals, int n_bins,
-                                                     uint32_t dense_end, uint32_t* __restrict__ bin_start,
-                                                     int4* __restrict__ pieces, int32_t* __restrict__ n_pieces,
+                                                     uint32_t* __restrict__ bin_start, int4* __restrict__ pieces,
+                                                     int32_t* __restrict__ n_pieces,
                                                      uint32_t* __restrict__ rec_max_bits) {
   if (threadIdx.x == 0) *rec_max_bits = 0u;
-  __shared__ uint32_t part_rec[1024], part_pc[1024];
+  __shared__ uint32_t part_rec[1024], part_pc[1024], part_sp[1024];
   const int t = threadIdx.x, nt = blockDim.x;
   const int per = (n_bins + nt - 1) / nt;
   const int b0 = t * per, b1 = min(n_bins, b0 + per);
-  uint32_t srec = 0, spc = 0;
+  uint32_t srec = 0, spc = 0, ssp = 0;
   for (int b = b0; b < b1; ++b) {
-    const uint32_t piece = kPiece;
+    const uint32_t np = (totals[b] + kPiece - 1) / kPiece;
     srec += totals[b];
-    spc += (totals[b] + piece - 1) / piece;
+    spc += np;
+    ssp += np > 1 ? 1u : 0u;
   }
   part_rec[t] = srec;
   part_pc[t] = spc;
+  part_sp[t] = ssp;
   __syncthreads();
   for (int o = 1; o < nt; o <<= 1) {
     const uint32_t ar = t >= o ? part_rec[t - o] : 0u, ap = t >= o ? part_pc[t - o] : 0u;
+    const uint32_t as = t >= o ? part_sp[t - o] : 0u;
     __syncthreads();
     part_rec[t] += ar;
     part_pc[t] += ap;
+    part_sp[t] += as;
     __syncthreads();
   }
-  uint32_t rec = part_rec[t] - srec, pc = part_pc[t] - spc;
+  uint32_t rec = part_rec[t] - srec, pc = part_pc[t] - spc, sp = part_sp[t] - ssp;
   for (int b = b0; b < b1; ++b) {
-    const uint32_t piece = kPiece;
     const uint32_t tot = totals[b];
     bin_start[b] = rec;
-    const uint32_t np = (tot + piece - 1) / piece;
+    const uint32_t np = (tot + kPiece - 1) / kPiece;
+    const int tag = np > 1 ? (int)(sp++) + 1 : 0;
     for (uint32_t k = 0; k < np; ++k)
-      pieces[pc + k] = make_int4(b, (int)(rec + k * piece), (int)min(piece, tot - k * piece), np > 1 ? 1 : 0);
+      pieces[pc + k] = make_int4(b, (int)(rec + k * kPiece), (int)min((uint32_t)kPiece, tot - k * kPiece), tag);
     rec += tot;
     pc += np;
   }
@@ -956,36 +975,35 @@ __global__ void __launch_bounds__(1024) k_bin_pieces(const uint32_t* __restrict_
 }
 
 // Reduces each piece of records in a 2^kBinBits-entry LDS tile (one pass over the piece per tile
-// when a bin spans several tiles), then adds the tile into the table gradient: a plain
-// read-add-write when the piece is the bin's only one (the block owns those entries), coalesced
-// atomics otherwise.  The tile accumulates in int64 fixed point (LDS integer
-// atomics are an order of magnitude faster than LDS float atomics on gfx950, and integer sums are
-// exact, so the result does not depend on record order).  Scale 2^e per bin: with c records in the
-// bin and every |record| <= vmax, |sum| <= c vmax < 2^61 2^-e, so nothing overflows; each record is
+// when a bin spans several tiles).  The tile accumulates in int64 fixed point (LDS integer atomics
+// are an order of magnitude faster than LDS float atomics on gfx950, and integer sums are exact, so
+// the result does not depend on record order).  Scale 2^e per bin: with c records in the bin and
+// every |record| <= vmax, |sum| <= c vmax < 2^61 2^-e, so no partial sum overflows; each record is
 // rounded once to a multiple of 2^-e (error <= 2^-e-1 = c vmax 2^-63).
-__global__ void __launch_bounds__(1024) k_bin_reduce(const BinRec* __restrict__ recs, const int4* __restrict__ pieces,
-                                                     const int32_t* __restrict__ n_pieces,
-                                                     const uint32_t* __restrict__ totals,
-                                                     const uint32_t* __restrict__ rec_max_bits,
-                                                     float* __restrict__ grad_table, int64_t n_entries,
-                                                     int bin_shift) {
+// A bin held by one piece adds its tile straight into the FP32 gradient (the block owns those
+// entries).  A bin cut into several pieces adds each piece's tile into its int64 accumulator with
+// global integer atomics; the piece that finishes last (per-tile counter) takes the sums out,
+// leaving the accumulator and counter at zero for the next step, and writes the gradient.
+__global__ void __launch_bounds__(1024) k_bin_reduce(const BinReduceArgs a) {
   extern __shared__ unsigned long long tile64[];
+  __shared__ int last;
   constexpr int NB = 1 << kBinBits;
-  const int np = *n_pieces;
-  const float vmax = __uint_as_float(*rec_max_bits);
-  const int n_sub = 1 << (bin_shift - kBinBits);
+  const int np = *a.n_pieces;
+  const float vmax = __uint_as_float(*a.rec_max_bits);
+  const int n_sub = a.n_sub;
   for (int job = blockIdx.x; job < np * n_sub; job += gridDim.x) {
     const int pc = job / n_sub, sub = job - pc * n_sub;
     for (int e = threadIdx.x; e < 2 * NB; e += blockDim.x) tile64[e] = 0ull;
     __syncthreads();
-    const int4 P = pieces[pc];
-    const uint32_t base = ((uint32_t)P.x << bin_shift) + ((uint32_t)sub << kBinBits);
+    const int4 P = a.pieces[pc];
+    const uint32_t base = ((uint32_t)P.x << a.bin_shift) + ((uint32_t)sub << kBinBits);
+    const uint32_t tot = a.totals[P.x];
     int ev, ec;
     frexpf(vmax, &ev);                                  // vmax < 2^ev
-    frexpf((float)totals[P.x] + 1.0f, &ec);             // count < 2^ec
+    frexpf((float)tot + 1.0f, &ec);                     // count < 2^ec
     const int e = 61 - ev - ec;
     const double up = ldexp(1.0, e), down = ldexp(1.0, -e);
-    const BinRec* __restrict__ src = recs + (size_t)P.y;
+    const BinRec* __restrict__ src = a.recs + (size_t)P.y;
     constexpr int U = 8;       // records in flight per thread; lane-contiguous (coalesced) loads
     for (int r0 = 0; r0 < P.z; r0 += blockDim.x * U) {
       BinRec rc[U];
@@ -1005,19 +1023,38 @@ __global__ void __launch_bounds__(1024) k_bin_reduce(const BinRec* __restrict__ 
       }
     }
     __syncthreads();
-    const int64_t lim = min((int64_t)NB, n_entries - (int64_t)base);
-    float2* g2 = reinterpret_cast<float2*>(grad_table) + base;
-    for (int q = threadIdx.x; q < lim; q += blockDim.x) {
-      const float2 v = make_float2((float)((double)(long long)tile64[2 * q] * down),
-                                   (float)((double)(long long)tile64[2 * q + 1] * down));
-      if (P.w) {   // the bin is split over several pieces: other blocks add to the same entries
-        if (v.x != 0.0f) atomicAdd(&g2[q].x, v.x);
-        if (v.y != 0.0f) atomicAdd(&g2[q].y, v.y);
-      } else {
+    const int64_t lim = min((int64_t)NB, a.n_entries - (int64_t)base);
+    float2* g2 = reinterpret_cast<float2*>(a.grad_table) + base;
+    if (P.w == 0) {
+      for (int q = threadIdx.x; q < lim; q += blockDim.x) {
         float2 o = g2[q];
-        o.x += v.x;
-        o.y += v.y;
+        o.x += (float)((double)(long long)tile64[2 * q] * down);
+        o.y += (float)((double)(long long)tile64[2 * q + 1] * down);
         g2[q] = o;
+      }
+    } else {
+      const size_t slot = (size_t)(P.w - 1) * n_sub + sub;
+      unsigned long long* acc = a.split_acc + slot * (2 * NB);
+      for (int q = threadIdx.x; q < 2 * lim; q += blockDim.x)
+        if (tile64[q] != 0ull) atomicAdd(acc + q, tile64[q]);
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint32_t pieces_of_bin = (tot + kPiece - 1) / kPiece;
+        last = atomicAdd(a.split_cnt + slot, 1u) == pieces_of_bin - 1;
+      }
+      __syncthreads();
+      if (last) {
+        __threadfence();
+        for (int q = threadIdx.x; q < lim; q += blockDim.x) {
+          const long long s0 = (long long)atomicExch(acc + 2 * q, 0ull);
+          const long long s1 = (long long)atomicExch(acc + 2 * q + 1, 0ull);
+          float2 o = g2[q];
+          o.x += (float)((double)s0 * down);
+          o.y += (float)((double)s1 * down);
+          g2[q] = o;
+        }
+        if (threadIdx.x == 0) atomicExch(a.split_cnt + slot, 0u);
       }
     }
     __syncthreads();
@@ -1135,8 +1172,8 @@ hipError_t launch_raysum(const float* ws, int wpr, int n_rays, float* out, hipSt
 
 hipError_t launch_reduce(const float* partials, int n_blocks, int nd_pad, int nd, float* grad_dense,
                          const float* absres, int n_rays, float inv_R, float* loss_out, hipStream_t s) {
-  k_reduce<<<(nd + 63) / 64, 256, 0, s>>>(partials, n_blocks, nd_pad, nd, grad_dense, absres, n_rays, inv_R,
-                                         loss_out);
+  k_reduce<<<(nd + 63) / 64, 1024, 0, s>>>(partials, n_blocks, nd_pad, nd, grad_dense, absres, n_rays, inv_R,
+                                          loss_out);
   return hipGetLastError();
 }
 
@@ -1178,22 +1215,20 @@ hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const 
   return hipGetLastError();
 }
 
-hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t dense_end, uint32_t* rel,
-                           uint32_t* totals, uint32_t* bin_start, int4* pieces, int32_t* n_pieces,
-                           uint32_t* rec_max_bits, hipStream_t s) {
+hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
+                           uint32_t* bin_start, int4* pieces, int32_t* n_pieces, uint32_t* rec_max_bits,
+                           hipStream_t s) {
   k_bin_rowscan<<<n_bins, 256, 0, s>>>(counts, grid, rel, totals);
-  k_bin_pieces<<<1, 1024, 0, s>>>(totals, n_bins, dense_end, bin_start, pieces, n_pieces, rec_max_bits);
+  k_bin_pieces<<<1, 1024, 0, s>>>(totals, n_bins, bin_start, pieces, n_pieces, rec_max_bits);
   return hipGetLastError();
 }
 
 size_t bin_reduce_lds() { return (size_t)2 * (1 << kBinBits) * sizeof(unsigned long long); }
 
-hipError_t launch_bin_reduce(const BinRec* recs, const int4* pieces, const int32_t* n_pieces, const uint32_t* totals,
-                             const uint32_t* rec_max_bits, float* grad_table, int64_t n_entries, int bin_shift,
-                             int grid, hipStream_t s) {
-  if (bin_shift < kBinBits || bin_shift > 31) return hipErrorInvalidValue;
-  k_bin_reduce<<<grid, 1024, bin_reduce_lds(), s>>>(recs, pieces, n_pieces, totals, rec_max_bits, grad_table,
-                                                    n_entries, bin_shift);
+hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s) {
+  if (a.bin_shift < kBinBits || a.bin_shift > 31 || a.n_sub != (1 << (a.bin_shift - kBinBits)))
+    return hipErrorInvalidValue;
+  k_bin_reduce<<<grid, 1024, bin_reduce_lds(), s>>>(a);
   return hipGetLastError();
 }
 
