@@ -38,6 +38,7 @@ nic_status fail(nic_status st, const char* fmt, ...) {
 
 constexpr int64_t kAlign = 256;
 constexpr int kMaxBwdBlocks = 2048;
+constexpr int kMaxReduceBlocks = 512 * 1024 / kReduceThreads;   // bin reduction grid (2 blocks of 1024 threads per CU on 256 CUs)
 constexpr int kLossHist = 4096;
 constexpr int kSqerrBlocks = 1024;
 
@@ -79,9 +80,8 @@ struct Plan {
   KernelSet ks;
   // workspace offsets (bytes)
   int64_t o_params, o_grads, o_m, o_v, o_th, o_part, o_rays, o_wsum, o_enc, o_apred, o_absres, o_loss, o_pix;
-  int64_t o_counts, o_offs, o_pieces, o_npieces, o_recs, o_totals, o_binstart, o_split, o_split_cnt;
+  int64_t o_counts, o_offs, o_recmax, o_recs, o_totals, o_binstart, o_bfb, o_split;
   int n_bins = 0;
-  int64_t max_pieces = 0, max_split = 0;
   int64_t bytes = 0;
 };
 
@@ -190,19 +190,16 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
     p.n_bins = (int)((ent + (1ll << sh) - 1) >> sh);
   }
   const int64_t max_recs = R * N * L * 8;
-  p.max_pieces = p.n_bins + max_recs / kPiece + 1;
-  // bins cut into several pieces hold more than kPiece records each
-  p.max_split = std::min<int64_t>(p.n_bins, max_recs / (kPiece + 1) + 1);
+  if (max_recs >= (1ll << 31)) { err = "too many gradient records per step (rays x samples x levels x 8 >= 2^31)"; return false; }
   const int64_t n_sub = 1ll << (p.lt.bin_shift - kBinBits);
   p.o_totals = take((int64_t)p.n_bins * 4);
-  p.o_binstart = take((int64_t)p.n_bins * 4);
+  p.o_binstart = take((int64_t)(p.n_bins + 1) * 4);
+  p.o_bfb = take((int64_t)kMaxReduceBlocks * 4);
   p.o_counts = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_offs = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
-  p.o_pieces = take(p.max_pieces * 16);
-  p.o_npieces = take(8);   // pieces, step's largest |record|
+  p.o_recmax = take(4);
   p.o_recs = take(max_recs * (int64_t)sizeof(BinRec));
-  p.o_split = take(p.max_split * n_sub * (2ll << kBinBits) * 8);
-  p.o_split_cnt = take(p.max_split * n_sub * 4);
+  p.o_split = take(2ll * kMaxReduceBlocks * n_sub * (2ll << kBinBits) * 8);
   p.o_sqerr = take(2 * kSqerrBlocks * 8);
   p.bytes = o;
   return true;
@@ -228,12 +225,10 @@ struct nic_model {
   RayRec* rays = nullptr;
   int32_t* pix = nullptr;
   uint32_t *counts = nullptr, *offs = nullptr, *totals = nullptr, *bin_start = nullptr;
-  int4* pieces = nullptr;
-  int32_t* n_pieces = nullptr;
+  int32_t* block_first_bin = nullptr;
   uint32_t* rec_max = nullptr;
   BinRec* recs = nullptr;
   unsigned long long* split_acc = nullptr;
-  uint32_t* split_cnt = nullptr;
   int reduce_grid = 0;
   double* sqerr = nullptr;
   const float* vols = nullptr;
@@ -359,8 +354,8 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   }
   {
     KTimer kt(m, 5);
-    NIC_HIP(launch_bin_scan(m->counts, pl.n_bins, grid, m->offs, m->totals, m->bin_start, m->pieces, m->n_pieces,
-                            m->rec_max, m->stream));
+    NIC_HIP(launch_bin_scan(m->counts, pl.n_bins, grid, m->offs, m->totals, m->bin_start, m->block_first_bin,
+                            m->reduce_grid, m->rec_max, m->stream));
   }
   b.enc_in = m->enc;
   b.a_pred_out = m->apred;
@@ -378,16 +373,15 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
     KTimer kt(m, 6);
     BinReduceArgs br{};
     br.recs = m->recs;
-    br.pieces = m->pieces;
-    br.n_pieces = m->n_pieces;
-    br.totals = m->totals;
+    br.bin_start = m->bin_start;
+    br.block_first_bin = m->block_first_bin;
+    br.n_bins = pl.n_bins;
     br.rec_max_bits = m->rec_max;
     br.grad_table = m->grads;
     br.n_entries = pl.n_entries * pl.n_tables;
     br.bin_shift = pl.lt.bin_shift;
     br.n_sub = 1 << (pl.lt.bin_shift - kBinBits);
     br.split_acc = m->split_acc;
-    br.split_cnt = m->split_cnt;
     NIC_HIP(launch_bin_reduce(br, m->reduce_grid, m->stream));
   }
   KTimer kt(m, 3);
@@ -519,13 +513,13 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   if (e == hipSuccess)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.ks.bwd, kBlock, p.ks.bwd_lds + bin_lds);
   if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_red, bin_reduce_kernel(), 1024, bin_reduce_lds());
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_red, bin_reduce_kernel(), kReduceThreads, bin_reduce_lds());
   if (e != hipSuccess) {
     delete m;
     return fail(NIC_EHIP, "device query: %s", hipGetErrorString(e));
   }
   m->bwd_grid = std::max(1, std::min(kMaxBwdBlocks, m->n_cu * std::max(1, per_cu)));
-  m->reduce_grid = std::max(1, m->n_cu * std::max(1, per_cu_red));
+  m->reduce_grid = std::max(1, std::min(kMaxReduceBlocks, m->n_cu * std::max(1, per_cu_red)));
 
   char* ws = (char*)workspace;
   m->ws = ws;
@@ -544,22 +538,15 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   m->pix = (int32_t*)(ws + p.o_pix);
   m->counts = (uint32_t*)(ws + p.o_counts);
   m->offs = (uint32_t*)(ws + p.o_offs);
-  m->pieces = (int4*)(ws + p.o_pieces);
-  m->n_pieces = (int32_t*)(ws + p.o_npieces);
-  m->rec_max = (uint32_t*)(ws + p.o_npieces + 4);
+  m->block_first_bin = (int32_t*)(ws + p.o_bfb);
+  m->rec_max = (uint32_t*)(ws + p.o_recmax);
   m->recs = (BinRec*)(ws + p.o_recs);
   m->split_acc = (unsigned long long*)(ws + p.o_split);
-  m->split_cnt = (uint32_t*)(ws + p.o_split_cnt);
   m->totals = (uint32_t*)(ws + p.o_totals);
   m->bin_start = (uint32_t*)(ws + p.o_binstart);
   m->sqerr = (double*)(ws + p.o_sqerr);
   *out = m;
-  // split-bin accumulators and counters start at zero; every step leaves them at zero
   nic_status st = NIC_OK;
-  if (launch_fill((float*)m->split_acc, (p.o_split_cnt - p.o_split) / 4, 0.0f, m->n_cu, m->stream) != hipSuccess ||
-      launch_fill((float*)m->split_cnt, p.max_split * (1ll << (p.lt.bin_shift - kBinBits)), 0.0f, m->n_cu,
-                  m->stream) != hipSuccess)
-    st = fail(NIC_EHIP, "workspace clear: %s", hipGetErrorString(hipGetLastError()));
   if (st == NIC_OK) st = nic_init_params(m, cfg->seed);
   if (st != NIC_OK) {
     delete m;

@@ -20,10 +20,7 @@ constexpr int kBinBits = 12;         // reduction tile: 2^12 entries (64 KB of i
 // the per-bin histogram fits in LDS beside the kernels' own tiles; a bin of more than one tile is
 // reduced tile by tile.
 constexpr int kLdsBytes = 160 * 1024;
-// Records reduced by one block in one pass.  A larger bin is split over several blocks, which add
-// their int64 tiles into a per-bin int64 accumulator; the last piece to finish converts it.
-// Integer sums make the table gradient exactly reproducible either way.
-constexpr int kPiece = 1 << 16;
+constexpr int kReduceThreads = 1024;  // threads of a bin-reduction block
 
 // One corner contribution to the table gradient: entry and the two feature gradients.
 struct BinRec {

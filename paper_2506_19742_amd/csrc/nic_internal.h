@@ -107,20 +107,20 @@ hipError_t launch_to_half(const float* src, __half* dst, int64_t n, int n_cu, hi
 hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const InitArgs& ia, int n_cu,
                        hipStream_t s);
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
-                           uint32_t* bin_start, int4* pieces, int32_t* n_pieces, uint32_t* rec_max_bits,
+                           uint32_t* bin_start, int32_t* block_first_bin, int reduce_grid, uint32_t* rec_max_bits,
                            hipStream_t s);
 struct BinReduceArgs {
   const BinRec* recs;             // records grouped by bin
-  const int4* pieces;             // (bin, first record, count, split slot + 1 or 0)
-  const int32_t* n_pieces;
-  const uint32_t* totals;         // records per bin
+  const uint32_t* bin_start;      // [n_bins + 1] first record of each bin; [n_bins] = total
+  const int32_t* block_first_bin; // [grid] bin holding the first record of each block's range
+  int32_t n_bins;
+  int32_t bin_shift;              // log2 entries per bin
+  int32_t n_sub;                  // 2^(bin_shift - kBinBits) LDS tiles per bin
+  int32_t pad_;
   const uint32_t* rec_max_bits;   // largest |record| of the step (float bits)
   float* grad_table;              // FP32 table gradient, [n_entries][2]
   int64_t n_entries;
-  int32_t bin_shift;              // log2 entries per bin
-  int32_t n_sub;                  // 2^(bin_shift - kBinBits) LDS tiles per bin
-  unsigned long long* split_acc;  // [slot][n_sub][2 << kBinBits] int64 accumulators of split bins, zero between steps
-  uint32_t* split_cnt;            // [slot][n_sub] pieces finished, zero between steps
+  unsigned long long* split_acc;  // [2 grid][n_sub][2 << kBinBits] int64 tiles of bins cut by range boundaries
 };
 hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s);
 size_t bin_reduce_lds();

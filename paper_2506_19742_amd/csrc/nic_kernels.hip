@@ -929,135 +929,179 @@ __global__ void __launch_bounds__(256) k_bin_rowscan(const uint32_t* __restrict_
   if (t == 255) totals[b] = part[255];
 }
 
-// Record offsets, step 2 (one block): bin starts and the list of reduction pieces (bin, first
-// record, count, split slot + 1 for a bin cut into several pieces, else 0).
-__global__ void __launch_bounds__(1024) k_bin_pieces(const uint32_t* __restrict__ totals, int n_bins,
-                                                     uint32_t* __restrict__ bin_start, int4* __restrict__ pieces,
-                                                     int32_t* __restrict__ n_pieces,
-                                                     uint32_t* __restrict__ rec_max_bits) {
+// Record offsets, step 2 (one block): bin starts (exclusive scan of the bin totals, with the total T
+// at index n_bins) and, for the bin reduction, the first bin of each block's record range.  The
+// reduction splits [0, T) evenly over G' = min(G, T) blocks: block j takes [T j / G', T (j+1) / G').
+__global__ void __launch_bounds__(1024) k_bin_plan(const uint32_t* __restrict__ totals, int n_bins, int G,
+                                                   uint32_t* __restrict__ bin_start,
+                                                   int32_t* __restrict__ block_first_bin,
+                                                   uint32_t* __restrict__ rec_max_bits) {
   if (threadIdx.x == 0) *rec_max_bits = 0u;
-  __shared__ uint32_t part_rec[1024], part_pc[1024], part_sp[1024];
+  __shared__ uint32_t part[1024];
   const int t = threadIdx.x, nt = blockDim.x;
   const int per = (n_bins + nt - 1) / nt;
   const int b0 = t * per, b1 = min(n_bins, b0 + per);
-  uint32_t srec = 0, spc = 0, ssp = 0;
-  for (int b = b0; b < b1; ++b) {
-    const uint32_t np = (totals[b] + kPiece - 1) / kPiece;
-    srec += totals[b];
-    spc += np;
-    ssp += np > 1 ? 1u : 0u;
-  }
-  part_rec[t] = srec;
-  part_pc[t] = spc;
-  part_sp[t] = ssp;
+  uint32_t srec = 0;
+  for (int b = b0; b < b1; ++b) srec += totals[b];
+  part[t] = srec;
   __syncthreads();
   for (int o = 1; o < nt; o <<= 1) {
-    const uint32_t ar = t >= o ? part_rec[t - o] : 0u, ap = t >= o ? part_pc[t - o] : 0u;
-    const uint32_t as = t >= o ? part_sp[t - o] : 0u;
+    const uint32_t ar = t >= o ? part[t - o] : 0u;
     __syncthreads();
-    part_rec[t] += ar;
-    part_pc[t] += ap;
-    part_sp[t] += as;
+    part[t] += ar;
     __syncthreads();
   }
-  uint32_t rec = part_rec[t] - srec, pc = part_pc[t] - spc, sp = part_sp[t] - ssp;
+  const uint64_t T = part[nt - 1];
+  const uint64_t Ge = T < (uint64_t)G ? T : (uint64_t)G;
+  uint32_t rec = part[t] - srec;
   for (int b = b0; b < b1; ++b) {
     const uint32_t tot = totals[b];
     bin_start[b] = rec;
-    const uint32_t np = (tot + kPiece - 1) / kPiece;
-    const int tag = np > 1 ? (int)(sp++) + 1 : 0;
-    for (uint32_t k = 0; k < np; ++k)
-      pieces[pc + k] = make_int4(b, (int)(rec + k * kPiece), (int)min((uint32_t)kPiece, tot - k * kPiece), tag);
+    if (tot > 0) {   // blocks j whose range starts inside [rec, rec + tot): ceil(rec G'/T) <= j < ceil((rec+tot) G'/T)
+      const uint64_t j0 = ((uint64_t)rec * Ge + T - 1) / T, j1 = ((uint64_t)(rec + tot) * Ge + T - 1) / T;
+      for (uint64_t jj = j0; jj < j1; ++jj) block_first_bin[jj] = b;
+    }
     rec += tot;
-    pc += np;
   }
-  if (t == nt - 1) *n_pieces = (int32_t)part_pc[t];
+  if (t == nt - 1) bin_start[n_bins] = (uint32_t)T;
 }
 
-// Reduces each piece of records in a 2^kBinBits-entry LDS tile (one pass over the piece per tile
-// when a bin spans several tiles).  The tile accumulates in int64 fixed point (LDS integer atomics
-// are an order of magnitude faster than LDS float atomics on gfx950, and integer sums are exact, so
-// the result does not depend on record order).  Scale 2^e per bin: with c records in the bin and
-// every |record| <= vmax, |sum| <= c vmax < 2^61 2^-e, so no partial sum overflows; each record is
-// rounded once to a multiple of 2^-e (error <= 2^-e-1 = c vmax 2^-63).
-// A bin held by one piece adds its tile straight into the FP32 gradient (the block owns those
-// entries).  A bin cut into several pieces adds each piece's tile into its int64 accumulator with
-// global integer atomics; the piece that finishes last (per-tile counter) takes the sums out,
-// leaving the accumulator and counter at zero for the next step, and writes the gradient.
-__global__ void __launch_bounds__(1024) k_bin_reduce(const BinReduceArgs a) {
+// Table gradient from the records.  Block j streams its even share of the records (grouped by bin)
+// and sums each bin's part in a 2^kBinBits-entry LDS tile (one pass over the part per tile when a
+// bin spans several tiles).  The tile accumulates in int64 fixed point: LDS integer atomics are an
+// order of magnitude faster than LDS float atomics on gfx950, and integer sums are exact, so the
+// result does not depend on record order.  Scale 2^e per bin: with c records in the bin and every
+// |record| <= vmax, |sum| <= c vmax < 2^61 2^-e, so no partial sum overflows; each record is rounded
+// once to a multiple of 2^-e (error <= 2^-e-1 = c vmax 2^-63).
+// A bin inside the block's range is added straight into the FP32 gradient (the block owns those
+// entries).  A bin cut by range boundaries is held by consecutive blocks j0..j1: each stores its
+// int64 tile in its own slot (2j for its first bin, 2j+1 for its last) and k_bin_combine adds the
+// slots in block order after the kernel ends (no cross-block synchronisation inside a kernel).
+__global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceArgs a) {
   extern __shared__ unsigned long long tile64[];
-  __shared__ int last;
   constexpr int NB = 1 << kBinBits;
-  const int np = *a.n_pieces;
+  const uint64_t T = a.bin_start[a.n_bins];
+  const uint64_t Ge = T < (uint64_t)gridDim.x ? T : (uint64_t)gridDim.x;
+  const uint64_t jb = blockIdx.x;
+  if (jb >= Ge) return;                                            // block-uniform
+  const uint32_t rs = (uint32_t)(T * jb / Ge), re = (uint32_t)(T * (jb + 1) / Ge);
   const float vmax = __uint_as_float(*a.rec_max_bits);
+  int ev;
+  frexpf(vmax, &ev);                                               // vmax < 2^ev
   const int n_sub = a.n_sub;
-  for (int job = blockIdx.x; job < np * n_sub; job += gridDim.x) {
-    const int pc = job / n_sub, sub = job - pc * n_sub;
-    for (int e = threadIdx.x; e < 2 * NB; e += blockDim.x) tile64[e] = 0ull;
-    __syncthreads();
-    const int4 P = a.pieces[pc];
-    const uint32_t base = ((uint32_t)P.x << a.bin_shift) + ((uint32_t)sub << kBinBits);
-    const uint32_t tot = a.totals[P.x];
-    int ev, ec;
-    frexpf(vmax, &ev);                                  // vmax < 2^ev
-    frexpf((float)tot + 1.0f, &ec);                     // count < 2^ec
+  for (int e2 = threadIdx.x; e2 < 2 * NB; e2 += blockDim.x) tile64[e2] = 0ull;
+  __syncthreads();
+  const int first_bin = a.block_first_bin[jb];
+  uint32_t pos = rs;
+  for (int B = first_bin; pos < re; ++B) {
+    const uint32_t b_start = a.bin_start[B], b_end = a.bin_start[B + 1];
+    if (b_end <= pos) continue;                                    // empty bin
+    const uint32_t seg_end = min(re, b_end);
+    const bool split = b_start < rs || b_end > re;
+    int ec;
+    frexpf((float)(b_end - b_start) + 1.0f, &ec);                  // count < 2^ec
     const int e = 61 - ev - ec;
     const double up = ldexp(1.0, e), down = ldexp(1.0, -e);
-    const BinRec* __restrict__ src = a.recs + (size_t)P.y;
-    constexpr int U = 8;       // records in flight per thread; lane-contiguous (coalesced) loads
-    for (int r0 = 0; r0 < P.z; r0 += blockDim.x * U) {
-      BinRec rc[U];
+    const size_t slot = 2 * (size_t)jb + (B == first_bin ? 0 : 1);
+    for (int sub = 0; sub < n_sub; ++sub) {
+      const uint32_t base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
+      const int64_t lim = min((int64_t)NB, a.n_entries - (int64_t)base);
+      float2* g2 = reinterpret_cast<float2*>(a.grad_table) + base;
+      // gradient entries of an owned bin, loaded now so the loads overlap the record stream
+      constexpr int PER = NB / kReduceThreads;
+      float2 o[PER];
+      if (!split) {
 #pragma unroll
-      for (int k = 0; k < U; ++k) {
-        const int r = r0 + k * blockDim.x + threadIdx.x;
-        if (r < P.z) rc[k] = src[r];
-      }
-#pragma unroll
-      for (int k = 0; k < U; ++k) {
-        const int r = r0 + k * blockDim.x + threadIdx.x;
-        const uint32_t q = rc[k].idx - base;   // wraps above NB for records of another tile
-        if (r < P.z && q < (uint32_t)NB) {
-          atomicAdd(tile64 + 2 * q, (unsigned long long)__double2ll_rn((double)rc[k].v0 * up));
-          atomicAdd(tile64 + 2 * q + 1, (unsigned long long)__double2ll_rn((double)rc[k].v1 * up));
+        for (int k = 0; k < PER; ++k) {
+          const int q = k * kReduceThreads + threadIdx.x;
+          if (q < lim) o[k] = g2[q];
         }
       }
+      const BinRec* __restrict__ src = a.recs + pos;
+      const int cnt = (int)(seg_end - pos);
+      constexpr int U = 8;       // records in flight per thread; lane-contiguous (coalesced) loads
+      for (int r0 = 0; r0 < cnt; r0 += kReduceThreads * U) {
+        BinRec rc[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const int r = r0 + k * kReduceThreads + threadIdx.x;
+          if (r < cnt) rc[k] = src[r];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const int r = r0 + k * kReduceThreads + threadIdx.x;
+          const uint32_t q = rc[k].idx - base;   // wraps above NB for records of another tile
+          if (r < cnt && q < (uint32_t)NB) {
+            atomicAdd(tile64 + 2 * q, (unsigned long long)__double2ll_rn((double)rc[k].v0 * up));
+            atomicAdd(tile64 + 2 * q + 1, (unsigned long long)__double2ll_rn((double)rc[k].v1 * up));
+          }
+        }
+      }
+      __syncthreads();
+      if (!split) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int q = k * kReduceThreads + threadIdx.x;
+          const long long s0 = (long long)tile64[2 * q], s1 = (long long)tile64[2 * q + 1];
+          tile64[2 * q] = 0ull;
+          tile64[2 * q + 1] = 0ull;
+          if (q < lim) {
+            o[k].x += (float)((double)s0 * down);
+            o[k].y += (float)((double)s1 * down);
+            g2[q] = o[k];
+          }
+        }
+      } else {
+        unsigned long long* S = a.split_acc + (slot * n_sub + sub) * (2 * NB);
+        for (int e2 = threadIdx.x; e2 < 2 * NB; e2 += kReduceThreads) {
+          S[e2] = tile64[e2];
+          tile64[e2] = 0ull;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    pos = seg_end;
+  }
+}
+
+// Bins cut by the range boundaries of k_bin_reduce: block j (1 <= j < G') takes the bin holding
+// record T j / G' when that bin starts inside block j - 1's range, adds the int64 slots of blocks
+// j0 = j - 1 .. j1 in order, and adds the result to the FP32 gradient.
+__global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
+  constexpr int NB = 1 << kBinBits;
+  const uint64_t T = a.bin_start[a.n_bins];
+  const uint64_t Ge = T < (uint64_t)gridDim.x ? T : (uint64_t)gridDim.x;
+  const uint64_t jb = blockIdx.x;
+  if (jb == 0 || jb >= Ge) return;
+  const uint32_t rs = (uint32_t)(T * jb / Ge), rs_prev = (uint32_t)(T * (jb - 1) / Ge);
+  const int B = a.block_first_bin[jb];
+  const uint32_t b_start = a.bin_start[B], b_end = a.bin_start[B + 1];
+  if (!(b_start < rs && b_start >= rs_prev)) return;     // not cut here, or cut at an earlier boundary
+  const uint32_t j0 = (uint32_t)jb - 1;
+  const uint32_t j1 = (uint32_t)(((uint64_t)b_end * Ge + T - 1) / T - 1);
+  const float vmax = __uint_as_float(*a.rec_max_bits);
+  int ev, ec;
+  frexpf(vmax, &ev);
+  frexpf((float)(b_end - b_start) + 1.0f, &ec);
+  const double down = ldexp(1.0, -(61 - ev - ec));
+  const int n_sub = a.n_sub;
+  for (int sub = 0; sub < n_sub; ++sub) {
+    const uint32_t base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
     const int64_t lim = min((int64_t)NB, a.n_entries - (int64_t)base);
     float2* g2 = reinterpret_cast<float2*>(a.grad_table) + base;
-    if (P.w == 0) {
-      for (int q = threadIdx.x; q < lim; q += blockDim.x) {
-        float2 o = g2[q];
-        o.x += (float)((double)(long long)tile64[2 * q] * down);
-        o.y += (float)((double)(long long)tile64[2 * q + 1] * down);
-        g2[q] = o;
+    for (int q = threadIdx.x; q < lim; q += blockDim.x) {
+      long long s0 = 0, s1 = 0;
+      for (uint32_t jj = j0; jj <= j1; ++jj) {
+        const size_t sl = 2 * (size_t)jj + (a.block_first_bin[jj] == B ? 0 : 1);
+        const unsigned long long* S = a.split_acc + (sl * n_sub + sub) * (2 * NB);
+        s0 += (long long)S[2 * q];
+        s1 += (long long)S[2 * q + 1];
       }
-    } else {
-      const size_t slot = (size_t)(P.w - 1) * n_sub + sub;
-      unsigned long long* acc = a.split_acc + slot * (2 * NB);
-      for (int q = threadIdx.x; q < 2 * lim; q += blockDim.x)
-        if (tile64[q] != 0ull) atomicAdd(acc + q, tile64[q]);
-      __threadfence();
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        const uint32_t pieces_of_bin = (tot + kPiece - 1) / kPiece;
-        last = atomicAdd(a.split_cnt + slot, 1u) == pieces_of_bin - 1;
-      }
-      __syncthreads();
-      if (last) {
-        __threadfence();
-        for (int q = threadIdx.x; q < lim; q += blockDim.x) {
-          const long long s0 = (long long)atomicExch(acc + 2 * q, 0ull);
-          const long long s1 = (long long)atomicExch(acc + 2 * q + 1, 0ull);
-          float2 o = g2[q];
-          o.x += (float)((double)s0 * down);
-          o.y += (float)((double)s1 * down);
-          g2[q] = o;
-        }
-        if (threadIdx.x == 0) atomicExch(a.split_cnt + slot, 0u);
-      }
+      float2 o = g2[q];
+      o.x += (float)((double)s0 * down);
+      o.y += (float)((double)s1 * down);
+      g2[q] = o;
     }
-    __syncthreads();
   }
 }
 
@@ -1216,10 +1260,10 @@ hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const 
 }
 
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
-                           uint32_t* bin_start, int4* pieces, int32_t* n_pieces, uint32_t* rec_max_bits,
+                           uint32_t* bin_start, int32_t* block_first_bin, int reduce_grid, uint32_t* rec_max_bits,
                            hipStream_t s) {
   k_bin_rowscan<<<n_bins, 256, 0, s>>>(counts, grid, rel, totals);
-  k_bin_pieces<<<1, 1024, 0, s>>>(totals, n_bins, bin_start, pieces, n_pieces, rec_max_bits);
+  k_bin_plan<<<1, 1024, 0, s>>>(totals, n_bins, reduce_grid, bin_start, block_first_bin, rec_max_bits);
   return hipGetLastError();
 }
 
@@ -1228,7 +1272,8 @@ size_t bin_reduce_lds() { return (size_t)2 * (1 << kBinBits) * sizeof(unsigned l
 hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s) {
   if (a.bin_shift < kBinBits || a.bin_shift > 31 || a.n_sub != (1 << (a.bin_shift - kBinBits)))
     return hipErrorInvalidValue;
-  k_bin_reduce<<<grid, 1024, bin_reduce_lds(), s>>>(a);
+  k_bin_reduce<<<grid, kReduceThreads, bin_reduce_lds(), s>>>(a);
+  k_bin_combine<<<grid, 1024, 0, s>>>(a);
   return hipGetLastError();
 }
 
