@@ -59,14 +59,15 @@ def measured_traffic(kernel: str, workload: str, precision: int):
 
 def algorithmic_bytes(cfg, lay, n_points):
     """Bytes the method itself moves per launch (independent of this implementation), for the
-    roofline: the encode gathers 8 corners x F features x 4 B per level and point (forward); the
-    scatter-add carries the same payload back (backward writes it as records, the bin reduction
-    folds it into the table gradient); dense Adam reads p, g, m, v and writes p, m, v, g (32 B per
-    parameter)."""
+    roofline: the encode gathers 8 corners x F features per level and point (4 B each, 2 B from the
+    FP16 table of the precision form; forward); the scatter-add carries 8 x F FP32 gradients per
+    level and point back (backward writes them as records, the bin reduction folds them into the
+    table gradient); dense Adam reads p, g, m, v and writes p, m, v, g (32 B per parameter)."""
     L, F = cfg.n_levels, cfg.feats_per_level
     payload = L * 8 * F * 4
+    gather = L * 8 * F * (2 if cfg.precision else 4)
     return {
-        "forward": n_points * payload,
+        "forward": n_points * gather,
         "backward": n_points * payload,
         "bin_reduce": n_points * payload,
         "adam": lay["n_params_padded"] * 32,
