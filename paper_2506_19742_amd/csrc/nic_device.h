@@ -286,6 +286,19 @@ __device__ __forceinline__ f32x16 mfma32_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
 
 __device__ __forceinline__ float xor32(float v) { return __shfl_xor(v, 32, 64); }
 
+// DPP lane moves within rows of 16 lanes (gfx9 encodings): row_shr:n brings lane l - n of the same row
+// (0 where that lane is outside the row), row_bcast:15 brings lane 15 of the previous row into rows 1
+// and 3 (rows 0 and 2 receive 0).
+constexpr int kDppRowShr = 0x110, kDppRowBcast15 = 0x142;
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+
 // Sum over the 32 lanes of one half (result in every lane of that half).
 __device__ __forceinline__ float half_sum(float v) {
 #pragma unroll

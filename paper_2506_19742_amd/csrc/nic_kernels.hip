@@ -178,22 +178,29 @@ __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restri
       bool cont, tail;
       run_flags(g0, g1, g2, ln, cont, tail);
       if (__ballot(cont) != 0) {            // wave-uniform: some lane continues a run
-        int start = cont ? 0 : ln;          // first lane of this lane's run (max-scan of run heads)
+        // Segmented inclusive scan over each half-wave on DPP moves: Hillis-Steele steps 1, 2, 4, 8
+        // inside each 16-lane row, then lanes 16..31 of the half add lane 15's sum when their run
+        // reaches back into the first row.  start = first lane of this lane's run (max-scan of run
+        // heads, same structure).
+        int start = cont ? 0 : ln;
+        start = max(start, dpp_i<kDppRowShr + 1, 0xF>(start));
+        start = max(start, dpp_i<kDppRowShr + 2, 0xF>(start));
+        start = max(start, dpp_i<kDppRowShr + 4, 0xF>(start));
+        start = max(start, dpp_i<kDppRowShr + 8, 0xF>(start));
+        start = max(start, dpp_i<kDppRowBcast15, 0xA>(start));
 #pragma unroll
-        for (int o = 1; o < 32; o <<= 1) {
-          const int t = __shfl_up(start, o, 32);
-          if (ln >= o && t > start) start = t;
-        }
-#pragma unroll
-        for (int o = 1; o < 32; o <<= 1) {
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            const float a0 = __shfl_up(v0[c], o, 32), a1 = __shfl_up(v1[c], o, 32);
-            if (ln - o >= start) {
-              v0[c] += a0;
-              v1[c] += a1;
-            }
-          }
+        for (int c = 0; c < 8; ++c) {
+          float a0, a1;
+          a0 = dpp_f<kDppRowShr + 1, 0xF>(v0[c]); a1 = dpp_f<kDppRowShr + 1, 0xF>(v1[c]);
+          if (ln - 1 >= start) { v0[c] += a0; v1[c] += a1; }
+          a0 = dpp_f<kDppRowShr + 2, 0xF>(v0[c]); a1 = dpp_f<kDppRowShr + 2, 0xF>(v1[c]);
+          if (ln - 2 >= start) { v0[c] += a0; v1[c] += a1; }
+          a0 = dpp_f<kDppRowShr + 4, 0xF>(v0[c]); a1 = dpp_f<kDppRowShr + 4, 0xF>(v1[c]);
+          if (ln - 4 >= start) { v0[c] += a0; v1[c] += a1; }
+          a0 = dpp_f<kDppRowShr + 8, 0xF>(v0[c]); a1 = dpp_f<kDppRowShr + 8, 0xF>(v1[c]);
+          if (ln - 8 >= start) { v0[c] += a0; v1[c] += a1; }
+          a0 = dpp_f<kDppRowBcast15, 0xA>(v0[c]); a1 = dpp_f<kDppRowBcast15, 0xA>(v1[c]);
+          if (ln >= 16 && start <= 15) { v0[c] += a0; v1[c] += a1; }
         }
       }
       if (active && tail) {

@@ -283,10 +283,11 @@ def test_rays_missing_the_box(ora):
     m.close()
 
 
-@pytest.mark.parametrize("N,depth", [(32, 1), (320, 2)])
-def test_other_shapes_forward_backward(ora, N, depth):
+@pytest.mark.parametrize("N,depth,ln", [(32, 1, 1), (320, 2, 1), (64, 3, 0)])
+def test_other_shapes_forward_backward(ora, N, depth, ln):
+    """Other sample counts and depths, and the encoder without its LayerNorm (plain hash encoding)."""
     w = synth.WORKLOADS["tiny64"]
-    cfg = nic.config_for(w, samples_per_ray=N, mlp_depth=depth, rays_per_step=96)
+    cfg = nic.config_for(w, samples_per_ray=N, mlp_depth=depth, rays_per_step=96, layernorm=ln)
     g = synth.cone_geometry(64, 50)
     ph = synth.make_phantom(1, 6)
     A = synth.project(ph, g).astype(np.float32)
