@@ -187,6 +187,12 @@ nic_status nic_zero_grad(nic_model* m);
  * (device float32 [n]). */
 nic_status nic_query(nic_model* m, const float* xn_dev, int64_t n, float* mu_dev);
 
+/* The feature-to-attenuation mapping alone (Sec. 2.3; Fig. 3 studies how it drifts for fixed
+ * features during training): LayerNorm (when enabled), MLP and output activation applied to n given
+ * encoder outputs enc_dev (device float32 [n][n_levels * 2], channel l * 2 + f, the layout
+ * nic_encode writes), into mu_dev (device float32 [n]).  Asynchronous on the model's stream. */
+nic_status nic_field_from_features(nic_model* m, const float* enc_dev, int64_t n, float* mu_dev);
+
 /* mu at the voxel centres ((i + 1/2)/nx, (j + 1/2)/ny, (k + 1/2)/nz) into vol_dev (device float32
  * [nz][ny][nx]); dims = {nx, ny, nz}. */
 nic_status nic_render_volume(nic_model* m, const int32_t dims[3], float* vol_dev);

@@ -74,6 +74,7 @@ def lib():
         L.ora_vertex_index.restype = C.c_uint32
         L.ora_encode.argtypes = [P(Cfg), d, f, C.c_int64, d, u32, d]
         L.ora_field.argtypes = [P(Cfg), d, f, C.c_int64, d, d, d]
+        L.ora_field_from_features.argtypes = [P(Cfg), d, d, C.c_int64, d]
         L.ora_field_backward.argtypes = [P(Cfg), d, f, C.c_int64, d, d]
         L.ora_ray_samples.argtypes = [P(Geom), C.c_double, C.c_int32, C.c_int32, f, f, d]
         L.ora_ray_samples.restype = C.c_int
@@ -231,6 +232,16 @@ def field(cfg: Config, params, xn, want=False):
     lib().ora_field(C.byref(cfg.c()), _p(params, C.c_double), _p(xn, C.c_float), n,
                     _p(mu, C.c_double), _p(enc, C.c_double), _p(z, C.c_double))
     return (mu, enc, z) if want else mu
+
+
+def field_from_features(cfg: Config, params, enc):
+    """mu from given encoder outputs [n][L*F] (LayerNorm + MLP + activation only)."""
+    params = _c64(params)
+    enc = _c64(enc).reshape(-1, cfg.n_levels * cfg.feats)
+    mu = np.zeros(enc.shape[0], np.float64)
+    lib().ora_field_from_features(C.byref(cfg.c()), _p(params, C.c_double), _p(enc, C.c_double),
+                                  enc.shape[0], _p(mu, C.c_double))
+    return mu
 
 
 def field_backward(cfg: Config, params, xn, dmu):

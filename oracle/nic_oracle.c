@@ -364,6 +364,8 @@ static double act_grad(const ora_cfg* c, double y) {
   return c->mu_max * s * (1.0 - s);
 }
 
+static void features_forward(const ora_cfg* c, const ora_layout* o, const double* d, point_state* st);
+
 static void point_forward(const ora_cfg* c, const ora_layout* o, const double* table, const double* d,
                           const float x[3], point_state* st) {
   for (int l = 0; l < o->L; ++l) {
@@ -374,6 +376,11 @@ static void point_forward(const ora_cfg* c, const ora_layout* o, const double* t
       st->enc[l * o->F + f] = s;
     }
   }
+  features_forward(c, o, d, st);
+}
+
+/* From the encoder output st->enc to mu: LayerNorm (Sec. 2.3), hidden layers, head, activation. */
+static void features_forward(const ora_cfg* c, const ora_layout* o, const double* d, point_state* st) {
   /* LayerNorm over the C channels of this point: biased variance, then gain and bias. */
   if (c->layernorm) {
     double m = 0.0;
@@ -476,6 +483,22 @@ void ora_field(const ora_cfg* c, const double* params, const float* xn, int64_t 
     mu[p] = st->mu;
     if (enc) for (int i = 0; i < o.C; ++i) enc[p * o.C + i] = st->enc[i];
     if (z) for (int i = 0; i < o.C; ++i) z[p * o.C + i] = st->z[i];
+  }
+  free(st);
+}
+
+/* mu from given encoder outputs enc [n][C] (channel l*F + f): the feature-to-attenuation mapping
+ * alone, as studied for fixed features in Fig. 3. */
+void ora_field_from_features(const ora_cfg* c, const double* params, const double* enc, int64_t n,
+                             double* mu) {
+  ora_layout o;
+  if (make_layout(c, &o)) return;
+  const double* dn = params + o.n_entries * o.F;
+  point_state* st = (point_state*)malloc(sizeof(point_state));
+  for (int64_t p = 0; p < n; ++p) {
+    for (int i = 0; i < o.C; ++i) st->enc[i] = enc[p * o.C + i];
+    features_forward(c, &o, dn, st);
+    mu[p] = st->mu;
   }
   free(st);
 }

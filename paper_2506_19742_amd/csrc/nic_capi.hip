@@ -751,6 +751,18 @@ nic_status nic_query(nic_model* m, const float* xn_dev, int64_t n, float* mu_dev
   return NIC_OK;
 }
 
+nic_status nic_field_from_features(nic_model* m, const float* enc_dev, int64_t n, float* mu_dev) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (n < 0) return fail(NIC_EINVAL, "n must be >= 0");
+  if (n == 0) return NIC_OK;
+  if (!enc_dev || !mu_dev) return fail(NIC_EINVAL, "NULL argument");
+  FwdArgs a = fwd_args(m, kModeFeatures, n);
+  a.feats = enc_dev;
+  a.mu_out = mu_dev;
+  NIC_HIP(launch_fwd(m->plan.ks, a, 0, 0, m->stream));
+  return NIC_OK;
+}
+
 nic_status nic_render_volume(nic_model* m, const int32_t dims[3], float* vol_dev) {
   if (!model_ok(m) || !dims || !vol_dev) return fail(NIC_EINVAL, "NULL argument");
   for (int k = 0; k < 3; ++k)

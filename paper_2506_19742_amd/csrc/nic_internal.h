@@ -9,7 +9,7 @@
 
 namespace nic {
 
-enum { kModeRays = 0, kModePoints = 1, kModeVoxels = 2, kModeVoxelLoss = 3 };
+enum { kModeRays = 0, kModePoints = 1, kModeVoxels = 2, kModeVoxelLoss = 3, kModeFeatures = 4 };
 
 struct FwdArgs {
   int32_t mode;          // kModeRays / kModePoints / kModeVoxels
@@ -29,6 +29,7 @@ struct FwdArgs {
   float ln_eps;
   int32_t dims[3];       // voxel grid (voxels mode)
   const float* xn;       // points mode [n][3]
+  const float* feats;    // features mode: encoder outputs [n][2L], channel l * 2 + f
   float* enc_out;        // rays mode: raw encoding, lane-major per wave (or NULL)
   float* wave_sum;       // rays mode: per-wave partial sums of mu * delta
   float* mu_out;         // points / voxels mode

@@ -539,9 +539,14 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_fwd(const FwdArgs a
     const uint32_t tbase = vloss ? (uint32_t)(p / a.pts_per_table) * a.table_stride : 0u;
 
     float e[RC];
-    // the bin histogram counts exactly the records the backward pass writes (hit rays only)
-    encode_half<L, P>(a.lt, a.table, x, h, e, hist != nullptr, (valid && (rr.hit || vloss)) ? hist : nullptr, n,
-                      tbase);
+    if (a.mode == kModeFeatures) {   // given encoder outputs: register r of half h is channel chan(r, h)
+#pragma unroll
+      for (int r = 0; r < RC; ++r) e[r] = valid ? a.feats[p * C + chan(r, h)] : 0.0f;
+    } else {
+      // the bin histogram counts exactly the records the backward pass writes (hit rays only)
+      encode_half<L, P>(a.lt, a.table, x, h, e, hist != nullptr, (valid && (rr.hit || vloss)) ? hist : nullptr,
+                        n, tbase);
+    }
     if (a.enc_out && wave_valid) {
 #pragma unroll
       for (int r = 0; r < RC; ++r) a.enc_out[(wave_id * RC + r) * kWave + lane] = e[r];

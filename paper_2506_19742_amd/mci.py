@@ -3,9 +3,13 @@
 1. ``reconstruct``: train the method on one scan (ray loss, Eq. 3) and track PSNR of the rendered
    volume against the ground truth over cumulative training time (evaluation time excluded).
 2. ``pretrain``: one hash table per pre-training volume and one shared LayerNorm + MLP, trained with
-   the voxel L1 loss (Eq. 2) on dense random points; returns the exported LN + MLP blob.
-3. ``transfer``: held-out reconstructions whose LN + MLP are imported from the blob (the hash table
-   stays freshly initialised), compared with random initialisation.
+   the voxel L1 loss (Eq. 2) on dense random points; returns the exported LN + MLP blob.  Stage
+   ``pretrain`` uses the method's own reconstructions of 16 phantoms as the volumes; stage
+   ``pretrain_gt`` follows the paper literally: the ground-truth volume of a single phantom.
+3. ``heldout``: held-out reconstructions whose LN + MLP are imported from a blob (the hash table
+   stays freshly initialised), compared with random initialisation.  An arm is
+   ``<fp32|bf16>_<random|mci|mcigt>[_noln]``; ``_noln`` drops the LayerNorm of the encoder (the
+   ablation of the Normalized Hash Encoder; an MCI blob is only loaded into a model of its own form).
 
 Every compute step runs in libnic's kernels; this module only sequences calls and records timings.
 Command line: ``python -m paper_2506_19742_amd.mci --help``.
@@ -98,9 +102,40 @@ def pretrain(cfg: nic.Config, vols, n_steps: int, n_points: int, log=None):
     return blob, {"seconds": dt, "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
 
 
+def stability(cfg: nic.Config, g, A, gt, n_steps: int, every: int, n_probe: int, seed: int, log=None):
+    """Fig. 3 analogue: every `every` steps, encode a fixed batch of points with the current table and
+    record the network's output on those features; `every` steps later, feed the same features to the
+    updated network and take the mean L1 change of its output.  Returns [(step, drift, relative drift,
+    PSNR)]."""
+    torch = _cuda()
+    dev = torch.device("cuda:0")
+    m = nic.Model(cfg, g)
+    m.set_projections(torch.tensor(A, device=dev))
+    gtd = torch.tensor(gt, device=dev)
+    n = gt.shape[0]
+    pts = torch.tensor(np.random.default_rng(seed).random((n_probe, 3)).astype(np.float32), device=dev)
+    prev = None
+    out = []
+    done = 0
+    while done < n_steps:
+        m.train(every, want_loss=False)
+        done += every
+        if prev is not None:
+            enc0, mu0 = prev
+            d = (m.field_from_features(enc0) - mu0).abs().mean().item()
+            out.append((done, d, d / max(mu0.abs().mean().item(), 1e-30), m.psnr(gtd, m.render_volume(n, n, n))))
+            if log:
+                log(f"  step {done:6d}  drift {out[-1][1]:.3e}  rel {out[-1][2]:.3e}  PSNR {out[-1][3]:.2f}")
+        enc = m.encode(pts)
+        prev = (enc, m.field_from_features(enc))
+    m.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--stage", choices=["calibrate", "pretrain", "heldout"], required=True)
+    ap.add_argument("--stage", choices=["calibrate", "pretrain", "pretrain_gt", "heldout", "stability"],
+                    required=True)
     ap.add_argument("--out", default="gpurun_out/mci")
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--depth", type=int, default=4)
@@ -114,14 +149,19 @@ def main(argv=None):
     ap.add_argument("--arms", default="fp32_random,bf16_mci,bf16_random,fp32_mci")
     ap.add_argument("--target", type=float, default=30.0)
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--gt-seed", type=int, default=1000)
+    ap.add_argument("--gt-grid", type=int, default=128)
+    ap.add_argument("--seed-base", type=int, default=2000)
+    ap.add_argument("--tag", default="")
     args = ap.parse_args(argv)
     import os
     os.makedirs(args.out, exist_ok=True)
     log = lambda s: print(s, flush=True)
     base = synth.WORKLOADS["ct256"]
 
-    def cfg_for(prec, seed):
-        return nic.config_for(base, mlp_width=args.width, mlp_depth=args.depth, precision=prec, seed=seed)
+    def cfg_for(prec, seed, ln=1):
+        return nic.config_for(base, mlp_width=args.width, mlp_depth=args.depth, precision=prec, seed=seed,
+                              layernorm=ln)
 
     if args.stage == "calibrate":
         ph, g, A, gt = scan_workload(256, 20, 2000, 50, 256, 1e5)
@@ -150,22 +190,45 @@ def main(argv=None):
         json.dump(info, open(f"{args.out}/pretrain.json", "w"))
         return
 
-    blob = open(f"{args.out}/mci_blob.bin", "rb").read()
+    if args.stage == "stability":
+        ph, g, A, gt = scan_workload(256, 20, args.seed_base, 50, 256, 1e5)
+        res = {}
+        for ln in (1, 0):
+            log(f"stability probe, phantom {args.seed_base}, LayerNorm {'on' if ln else 'off'}")
+            res[f"ln{ln}"] = stability(cfg_for(0, 7, ln), g, A, gt, args.steps, args.eval_every, 1 << 16, 5, log=log)
+        json.dump(res, open(f"{args.out}/stability{args.tag}.json", "w"))
+        return
+
+    if args.stage == "pretrain_gt":
+        ph = synth.make_phantom(args.gt_seed, 20)
+        vol = synth.voxelize(ph, args.gt_grid).astype(np.float32)[None]
+        blob, info = pretrain(cfg_for(0, 99), vol, args.pre_steps, args.pre_points, log=log)
+        info["gt_seed"] = args.gt_seed
+        open(f"{args.out}/mci_blob_gt.bin", "wb").write(blob)
+        json.dump(info, open(f"{args.out}/pretrain_gt.json", "w"))
+        return
+
+    blobs = {}
+    for name, path in (("mci", "mci_blob.bin"), ("mcigt", "mci_blob_gt.bin")):
+        if os.path.exists(f"{args.out}/{path}"):
+            blobs[name] = open(f"{args.out}/{path}", "rb").read()
     results = {}
     for i in range(args.n_heldout):
-        seed = 2000 + i
+        seed = args.seed_base + i
         ph, g, A, gt = scan_workload(256, 20, seed, 50, 256, 1e5)
         for arm in args.arms.split(","):
-            prec = 1 if arm.startswith("bf16") else 0
-            use = blob if arm.endswith("mci") else None
+            parts = arm.split("_")
+            prec = 1 if parts[0] == "bf16" else 0
+            ln = 0 if "noln" in parts[2:] else 1
+            use = None if parts[1] == "random" else blobs[parts[1]]
             log(f"held-out {seed} arm {arm}")
-            r = reconstruct(cfg_for(prec, 3000 + i), g, A, gt, args.steps, args.eval_every, args.target, blob=use,
-                            log=None)
+            r = reconstruct(cfg_for(prec, 3000 + i, ln), g, A, gt, args.steps, args.eval_every, args.target,
+                            blob=use, log=None)
             r["model"].close()
             best = max(p for _, _, p in r["curve"])
             log(f"  -> hit {r['hit']}, best {best:.2f} dB")
             results.setdefault(arm, {})[seed] = {"curve": r["curve"], "hit": r["hit"]}
-        json.dump(results, open(f"{args.out}/heldout.json", "w"))
+        json.dump(results, open(f"{args.out}/heldout{args.tag}.json", "w"))
 
 
 if __name__ == "__main__":

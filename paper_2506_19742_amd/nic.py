@@ -60,7 +60,7 @@ EXPORTS = ["nic_describe", "nic_workspace_size", "nic_create", "nic_destroy", "n
            "nic_adam", "nic_zero_grad", "nic_query", "nic_render_volume", "nic_encode",
            "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step",
            "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr",
-           "nic_save_state", "nic_load_state"]
+           "nic_save_state", "nic_load_state", "nic_field_from_features"]
 
 _lib = None
 
@@ -105,6 +105,7 @@ def lib():
             "nic_psnr": ([vp, vp, vp, C.c_int64, P(C.c_double)], C.c_int32),
             "nic_save_state": ([vp, vp, P(C.c_size_t)], C.c_int32),
             "nic_load_state": ([vp, vp, C.c_size_t], C.c_int32),
+            "nic_field_from_features": ([vp, vp, C.c_int64, vp], C.c_int32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -294,6 +295,16 @@ class Model:
         torch = self.torch
         mu = torch.empty(xn.shape[0], dtype=torch.float32, device=self.ws.device)
         _check(lib().nic_query(self.h, _ptr(xn), xn.shape[0], _ptr(mu)))
+        return mu
+
+    def field_from_features(self, enc):
+        """mu from given encoder outputs [n][2L] (LayerNorm + MLP + output activation only)."""
+        torch = self.torch
+        if enc.dim() != 2 or enc.shape[1] != 2 * self.cfg.n_levels or enc.dtype != torch.float32 \
+                or not enc.is_contiguous():
+            raise ValueError(f"enc must be contiguous float32 [n][{2 * self.cfg.n_levels}]")
+        mu = torch.empty(enc.shape[0], dtype=torch.float32, device=self.ws.device)
+        _check(lib().nic_field_from_features(self.h, _ptr(enc), enc.shape[0], _ptr(mu)))
         return mu
 
     def render_volume(self, nx: int, ny: int, nz: int):

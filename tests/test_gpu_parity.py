@@ -124,6 +124,25 @@ def test_query_matches_oracle(ora, tiny, scale):
     assert rel(mu, ora.field(c.oc, p, x)) <= FWD_TOL
 
 
+def test_field_from_features_matches_oracle(ora, tiny):
+    """LayerNorm + MLP + activation on given encoder outputs (the mapping Fig. 3 tracks), fed with the
+    GPU's own encoding of 1001 points and with arbitrary feature vectors."""
+    c = tiny
+    p = random_params(ora, c.oc, 8, 0.1)
+    c.set_params(p)
+    x = _pts(1001, 9)
+    tx = torch.tensor(x, device="cuda")
+    enc = c.model.encode(tx)
+    mu = c.model.field_from_features(enc).cpu().numpy()
+    assert rel(mu, ora.field_from_features(c.oc, p, enc.cpu().numpy().astype(np.float64))) <= FWD_TOL
+    assert rel(mu, c.model.query(tx).cpu().numpy()) <= 1e-6
+    f = (np.random.default_rng(10).standard_normal((77, 2 * c.cfg.n_levels)) * 0.3).astype(np.float32)
+    mu2 = c.model.field_from_features(torch.tensor(f, device="cuda")).cpu().numpy()
+    assert rel(mu2, ora.field_from_features(c.oc, p, f.astype(np.float64))) <= FWD_TOL
+    with pytest.raises(ValueError):
+        c.model.field_from_features(torch.zeros((3, 5), device="cuda"))
+
+
 def test_render_volume_matches_oracle(ora, tiny):
     c = tiny
     p = random_params(ora, c.oc, 7, 0.1)

@@ -636,3 +636,32 @@ def test_init_params_distribution(ora):
     o, n = lay["W1"]; assert np.abs(p[nt + o:nt + o + n]).max() <= 1 / math.sqrt(cfg.width)
     o, n = lay["W0"]; C = cfg.n_levels * cfg.feats
     assert np.abs(p[nt + o:nt + o + n]).max() <= 1 / math.sqrt(C)
+
+
+@pytest.mark.parametrize("layernorm", [1, 0])
+def test_field_from_features_pins(ora, layernorm):
+    """The feature-to-attenuation mapping alone (Sec. 2.3, Fig. 3): composed with the encoder it is
+    the field; with a zero network it is the constant mu_max sigmoid(b_out); with LayerNorm a shift
+    of all channels of a point changes nothing (the mean is removed), without it the shift shows."""
+    cfg = ora.Config(**CFG_SMALL, layernorm=layernorm)
+    tot, nt, nd = ora.n_params(cfg)
+    rng = np.random.default_rng(71)
+    params = rng.standard_normal(tot) * 0.5
+    x = rng.random((40, 3)).astype(np.float32)
+    mu, enc, _ = ora.field(cfg, params, x, want=True)
+    assert np.array_equal(ora.field_from_features(cfg, params, enc), mu)
+    lay = ora.dense_layout(cfg)
+    zero = params.copy()
+    zero[nt:] = 0.0
+    o, n = lay["ln_g"]
+    zero[nt + o:nt + o + n] = 1.0
+    b = 0.37
+    zero[nt + lay["b_out"][0]] = b
+    feats = rng.standard_normal((25, enc.shape[1]))
+    want = 0.25 / (1.0 + np.exp(-b))
+    assert np.allclose(ora.field_from_features(cfg, zero, feats), want, rtol=0, atol=1e-15)
+    shifted = ora.field_from_features(cfg, params, enc + 0.3)
+    if layernorm:
+        assert np.allclose(shifted, mu, rtol=1e-12, atol=1e-15)
+    else:
+        assert np.abs(shifted - mu).max() > 1e-6
