@@ -236,6 +236,7 @@ struct nic_model {
   const float* proj = nullptr;
   int64_t step = 0;
   int64_t epoch_cached = -1;
+  bool grads_dirty = false;   // gradients accumulated by nic_backward and not yet consumed by Adam
   std::vector<int32_t> epoch_order;
   // kernel timing (benchmarks)
   bool timing = false;
@@ -320,10 +321,19 @@ nic_status rays(nic_model* m, int32_t view, const int32_t* pix_in, int32_t n_ray
   return NIC_OK;
 }
 
+AdamArgs adam_args(const nic_model* m) {
+  const int64_t t = m->step + 1;
+  const double bc1 = 1.0 - std::pow(m->cfg.beta1, (double)t);
+  const double bc2 = 1.0 - std::pow(m->cfg.beta2, (double)t);
+  return AdamArgs{(float)m->cfg.lr, (float)m->cfg.beta1, (float)m->cfg.beta2, (float)m->cfg.adam_eps,
+                  (float)(1.0 / bc1), (float)(1.0 / bc2)};
+}
+
 nic_status adam(nic_model* m) {
   const int64_t t = m->step + 1;
   const double bc1 = 1.0 - std::pow(m->cfg.beta1, (double)t);
   const double bc2 = 1.0 - std::pow(m->cfg.beta2, (double)t);
+  m->grads_dirty = false;
   KTimer kt(m, 4);
   NIC_HIP(launch_adam(m->params, m->grads, m->m, m->v, m->plan.n_params_pad, (float)m->cfg.lr, (float)m->cfg.beta1,
                       (float)m->cfg.beta2, (float)m->cfg.adam_eps, (float)(1.0 / bc1), (float)(1.0 / bc2), m->th,
@@ -336,9 +346,11 @@ nic_status adam(nic_model* m) {
 // counts the table-gradient records per (bin, block); the scan turns the counts into write
 // offsets; the backward pass writes its records there; the bin reduction sums them into the table
 // gradient.  loss_src/loss_n/loss_scale: the per-ray (or per-wave) absolute residuals whose scaled
-// sum is the loss written to loss_dev (when not NULL).
+// sum is the loss written to loss_dev (when not NULL).  fused: the step's Adam update runs inside
+// the reductions (table in k_bin_reduce / k_bin_combine, LN + MLP in k_reduce) instead of a
+// separate pass over stored gradients; only valid when the gradients start at zero.
 nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, int32_t loss_n, float loss_scale,
-                   float* loss_dev) {
+                   float* loss_dev, bool fused) {
   const Plan& pl = m->plan;
   const int64_t P = a.n_points;
   const int64_t chunks = (P + kPtsPerBlock - 1) / kPtsPerBlock;
@@ -382,26 +394,39 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
     br.bin_shift = pl.lt.bin_shift;
     br.n_sub = 1 << (pl.lt.bin_shift - kBinBits);
     br.split_acc = m->split_acc;
+    br.fused = fused ? 1 : 0;
+    br.adam = adam_args(m);
+    br.p = m->params;
+    br.m = m->m;
+    br.v = m->v;
+    br.th = m->th;
     NIC_HIP(launch_bin_reduce(br, m->reduce_grid, m->stream));
   }
-  KTimer kt(m, 3);
-  NIC_HIP(launch_reduce(m->partials, grid, pl.nd_pad, (int)pl.n_dense, m->grads + pl.dense_off, loss_src, loss_n,
-                        loss_scale, loss_dev, m->stream));
+  {
+    KTimer kt(m, 3);
+    const AdamArgs A = adam_args(m);
+    NIC_HIP(launch_reduce(m->partials, grid, pl.nd_pad, (int)pl.n_dense, m->grads + pl.dense_off, loss_src, loss_n,
+                          loss_scale, loss_dev, fused ? &A : nullptr, m->params + pl.dense_off,
+                          m->m + pl.dense_off, m->v + pl.dense_off, m->stream));
+  }
+  if (fused) m->step += 1;
+  else m->grads_dirty = true;
   return NIC_OK;
 }
 
 // Ray training pass over the rays currently in m->rays (dA == NULL: L1 loss of Eq. 3).
-nic_status ray_fwd_bwd(nic_model* m, int32_t n_rays, const float* jitter, const float* dA, float* loss_dev) {
+nic_status ray_fwd_bwd(nic_model* m, int32_t n_rays, const float* jitter, const float* dA, float* loss_dev,
+                       bool fused) {
   FwdArgs a = fwd_args(m, kModeRays, (int64_t)n_rays * m->cfg.samples_per_ray);
   a.jitter = jitter;
   BwdArgs b{};
   b.dA_in = dA;
   b.inv_R = 1.0f / (float)n_rays;
-  return fwd_bwd(m, a, b, m->absres, n_rays, 1.0f / (float)n_rays, dA ? nullptr : loss_dev);
+  return fwd_bwd(m, a, b, m->absres, n_rays, 1.0f / (float)n_rays, dA ? nullptr : loss_dev, fused);
 }
 
 // Voxel-loss pass (Eq. 2) over n_points points.
-nic_status voxel_fwd_bwd(nic_model* m, const float* xn, int32_t n_points, float* loss_dev) {
+nic_status voxel_fwd_bwd(nic_model* m, const float* xn, int32_t n_points, float* loss_dev, bool fused) {
   FwdArgs a = fwd_args(m, kModeVoxelLoss, n_points);
   a.xn = xn;
   a.pts_per_table = n_points / m->plan.n_tables;
@@ -411,7 +436,21 @@ nic_status voxel_fwd_bwd(nic_model* m, const float* xn, int32_t n_points, float*
   BwdArgs b{};
   b.inv_R = 1.0f / (float)n_points;
   b.wave_loss = m->wsum;
-  return fwd_bwd(m, a, b, m->wsum, n_points / kPtsPerWave, 1.0f / (float)n_points, loss_dev);
+  return fwd_bwd(m, a, b, m->wsum, n_points / kPtsPerWave, 1.0f / (float)n_points, loss_dev, fused);
+}
+
+// One training step over prepared rays: fused Adam when no gradients are pending, else the
+// gradients of this pass are added to the pending ones and a separate Adam pass consumes them.
+nic_status ray_train_step(nic_model* m, int32_t n_rays, const float* jitter, float* loss_dev) {
+  if (!m->grads_dirty) return ray_fwd_bwd(m, n_rays, jitter, nullptr, loss_dev, true);
+  nic_status st = ray_fwd_bwd(m, n_rays, jitter, nullptr, loss_dev, false);
+  return st ? st : adam(m);
+}
+
+nic_status voxel_train_step(nic_model* m, const float* xn, int32_t n_points, float* loss_dev) {
+  if (!m->grads_dirty) return voxel_fwd_bwd(m, xn, n_points, loss_dev, true);
+  nic_status st = voxel_fwd_bwd(m, xn, n_points, loss_dev, false);
+  return st ? st : adam(m);
 }
 
 bool model_ok(const nic_model* m) { return m != nullptr && m->ws != nullptr; }
@@ -603,6 +642,7 @@ nic_status nic_init_params(nic_model* m, uint64_t seed) {
   ia.width = W;
   NIC_HIP(launch_fill(m->params, p.n_params_pad, 0.0f, m->n_cu, m->stream));
   NIC_HIP(launch_fill(m->grads, p.n_params_pad, 0.0f, m->n_cu, m->stream));
+  m->grads_dirty = false;
   NIC_HIP(launch_fill(m->m, p.n_params_pad, 0.0f, m->n_cu, m->stream));
   NIC_HIP(launch_fill(m->v, p.n_params_pad, 0.0f, m->n_cu, m->stream));
   NIC_HIP(launch_init(m->params, p.n_table, p.dense_off, ia, m->n_cu, m->stream));
@@ -666,9 +706,7 @@ nic_status nic_step(nic_model* m, int32_t view, const int32_t* pix_dev, const fl
   const int32_t R = m->cfg.rays_per_step;
   nic_status st = rays(m, view, pix_dev, R, (uint32_t)m->step, nullptr, nullptr);
   if (st) return st;
-  st = ray_fwd_bwd(m, R, jitter_dev, nullptr, loss_dev ? loss_dev : m->loss);
-  if (st) return st;
-  return adam(m);
+  return ray_train_step(m, R, jitter_dev, loss_dev ? loss_dev : m->loss);
 }
 
 nic_status nic_train(nic_model* m, int32_t n_steps, float* loss_host) {
@@ -682,9 +720,7 @@ nic_status nic_train(nic_model* m, int32_t n_steps, float* loss_host) {
       const int32_t view = nic_view_for_step(m, m->step);
       nic_status st = rays(m, view, nullptr, m->cfg.rays_per_step, (uint32_t)m->step, nullptr, nullptr);
       if (st) return st;
-      st = ray_fwd_bwd(m, m->cfg.rays_per_step, nullptr, nullptr, m->loss + k);
-      if (st) return st;
-      st = adam(m);
+      st = ray_train_step(m, m->cfg.rays_per_step, nullptr, m->loss + k);
       if (st) return st;
     }
     if (loss_host) {
@@ -725,7 +761,7 @@ nic_status nic_backward(nic_model* m, int32_t view, const int32_t* pix_dev, cons
   if (n_rays == 0) return NIC_OK;
   nic_status st = rays(m, view, pix_dev, n_rays, (uint32_t)m->step, nullptr, nullptr);
   if (st) return st;
-  return ray_fwd_bwd(m, n_rays, jitter_dev, dA_dev, nullptr);
+  return ray_fwd_bwd(m, n_rays, jitter_dev, dA_dev, nullptr, false);
 }
 
 nic_status nic_adam(nic_model* m) {
@@ -736,6 +772,7 @@ nic_status nic_adam(nic_model* m) {
 nic_status nic_zero_grad(nic_model* m) {
   if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
   NIC_HIP(launch_fill(m->grads, m->plan.n_params_pad, 0.0f, m->n_cu, m->stream));
+  m->grads_dirty = false;
   return NIC_OK;
 }
 
@@ -807,9 +844,7 @@ nic_status nic_voxel_step(nic_model* m, const float* xn_dev, int32_t n_points, f
   if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
   nic_status st = check_voxel_args(m, n_points);
   if (st) return st;
-  st = voxel_fwd_bwd(m, xn_dev, n_points, loss_dev ? loss_dev : m->loss);
-  if (st) return st;
-  return adam(m);
+  return voxel_train_step(m, xn_dev, n_points, loss_dev ? loss_dev : m->loss);
 }
 
 nic_status nic_voxel_train(nic_model* m, int32_t n_steps, int32_t n_points, float* loss_host) {
@@ -821,9 +856,7 @@ nic_status nic_voxel_train(nic_model* m, int32_t n_steps, int32_t n_points, floa
   for (int32_t k0 = 0; k0 < n_steps; k0 += kLossHist) {
     const int32_t kn = std::min<int32_t>(kLossHist, n_steps - k0);
     for (int32_t k = 0; k < kn; ++k) {
-      st = voxel_fwd_bwd(m, nullptr, n_points, m->loss + k);
-      if (st) return st;
-      st = adam(m);
+      st = voxel_train_step(m, nullptr, n_points, m->loss + k);
       if (st) return st;
     }
     if (loss_host) {
@@ -934,6 +967,7 @@ nic_status nic_load_state(nic_model* m, const void* buf, size_t bytes) {
   NIC_HIP(hipMemcpyAsync(m->m, src + n, n, hipMemcpyHostToDevice, m->stream));
   NIC_HIP(hipMemcpyAsync(m->v, src + 2 * n, n, hipMemcpyHostToDevice, m->stream));
   NIC_HIP(launch_fill(m->grads, m->plan.n_params_pad, 0.0f, m->n_cu, m->stream));
+  m->grads_dirty = false;
   if (m->th) NIC_HIP(launch_to_half(m->params, m->th, m->plan.n_table, m->n_cu, m->stream));
   NIC_HIP(hipStreamSynchronize(m->stream));
   m->step = h.step;

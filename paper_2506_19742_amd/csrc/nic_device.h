@@ -286,6 +286,17 @@ __device__ __forceinline__ f32x16 mfma32_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
 
 __device__ __forceinline__ float xor32(float v) { return __shfl_xor(v, 32, 64); }
 
+// Adam (Kingma and Ba, Algorithm 1) on one parameter; ibc1, ibc2 = 1 / (1 - beta^t).
+struct AdamArgs {
+  float lr, b1, b2, eps, ibc1, ibc2;
+};
+__device__ __forceinline__ void adam_update(float& p, float& m, float& v, float g, const AdamArgs& A) {
+  m = A.b1 * m + (1.0f - A.b1) * g;
+  v = A.b2 * v + (1.0f - A.b2) * g * g;
+  const float mh = m * A.ibc1, vh = v * A.ibc2;
+  p -= A.lr * mh / (sqrtf(vh) + A.eps);
+}
+
 // DPP lane moves within rows of 16 lanes (gfx9 encodings): row_shr:n brings lane l - n of the same row
 // (0 where that lane is outside the row), row_bcast:15 brings lane 15 of the previous row into rows 1
 // and 3 (rows 0 and 2 receive 0).

@@ -99,8 +99,11 @@ hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, i
                       hipStream_t s);
 hipError_t launch_rays(const RaysArgs& a, hipStream_t s);
 hipError_t launch_raysum(const float* wave_sum, int waves_per_ray, int n_rays, float* out, hipStream_t s);
+// Dense gradient and loss; with adam != NULL also Adam on the dense parameters p/m/v (gradient
+// consumed and zeroed).
 hipError_t launch_reduce(const float* partials, int n_blocks, int nd_pad, int nd, float* grad_dense,
-                         const float* absres, int n_rays, float inv_R, float* loss_out, hipStream_t s);
+                         const float* absres, int n_rays, float inv_R, float* loss_out, const AdamArgs* adam,
+                         float* p, float* m, float* v, hipStream_t s);
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, float ibc1, float ibc2, __half* th, int64_t n_table, int n_cu, hipStream_t s);
 hipError_t launch_fill(float* x, int64_t n, float val, int n_cu, hipStream_t s);
@@ -122,6 +125,14 @@ struct BinReduceArgs {
   float* grad_table;              // FP32 table gradient, [n_entries][2]
   int64_t n_entries;
   unsigned long long* split_acc;  // [2 grid][n_sub][2 << kBinBits] int64 tiles of bins cut by range boundaries
+  // Fused Adam (training steps whose gradients start at zero): the table gradient is never stored;
+  // each entry's gradient goes straight into Adam on p/m/v (and the FP16 copy th when not NULL).
+  int32_t fused;
+  AdamArgs adam;
+  float* p;                       // table parameters, Adam moments [n_entries][2]
+  float* m;
+  float* v;
+  __half* th;
 };
 hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s);
 size_t bin_reduce_lds();

@@ -809,11 +809,14 @@ __global__ void k_raysum(const float* __restrict__ wave_sum, int waves_per_ray, 
 }
 
 // grad_dense[k] += sum_g partials[g][k] (fixed order: 16 strided groups, then the groups in order);
-// block 0 also forms loss = sum_r absres[r] * inv_R.
+// block 0 also forms loss = sum_r absres[r] * inv_R.  With fused != 0 the summed gradient goes into
+// Adam on the dense parameters p/m/v instead and grad_dense is left at zero.
 __global__ void __launch_bounds__(1024) k_reduce(const float* __restrict__ partials, int n_blocks, int nd_pad,
                                                  int nd, float* __restrict__ grad_dense,
                                                  const float* __restrict__ absres, int n_rays, float inv_R,
-                                                 float* __restrict__ loss_out) {
+                                                 float* __restrict__ loss_out, int fused, AdamArgs A,
+                                                 float* __restrict__ pd, float* __restrict__ md,
+                                                 float* __restrict__ vd) {
   __shared__ float red[1024];
   const int k = blockIdx.x * 64 + (threadIdx.x & 63);
   const int grp = threadIdx.x >> 6;
@@ -834,7 +837,16 @@ __global__ void __launch_bounds__(1024) k_reduce(const float* __restrict__ parti
     float t = 0.0f;
 #pragma unroll
     for (int q = 0; q < 16; ++q) t += red[threadIdx.x + 64 * q];
-    grad_dense[k] += t;
+    if (fused) {
+      float pp = pd[k], mm = md[k], vv = vd[k];
+      adam_update(pp, mm, vv, grad_dense[k] + t, A);
+      pd[k] = pp;
+      md[k] = mm;
+      vd[k] = vv;
+      grad_dense[k] = 0.0f;
+    } else {
+      grad_dense[k] += t;
+    }
   }
   if (blockIdx.x == 0 && loss_out) {
     __syncthreads();
@@ -863,13 +875,9 @@ __global__ void k_adam(float4* __restrict__ p, float4* __restrict__ g, float4* _
     float* G = &gg.x;
     float* M = &mm.x;
     float* V = &vv.x;
+    const AdamArgs A{lr, b1, b2, eps, ibc1, ibc2};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      M[k] = b1 * M[k] + (1.0f - b1) * G[k];
-      V[k] = b2 * V[k] + (1.0f - b2) * G[k] * G[k];
-      const float mh = M[k] * ibc1, vh = V[k] * ibc2;
-      P[k] -= lr * mh / (sqrtf(vh) + eps);
-    }
+    for (int k = 0; k < 4; ++k) adam_update(P[k], M[k], V[k], G[k], A);
     p[q] = pp;
     m[q] = mm;
     v[q] = vv;
@@ -986,9 +994,11 @@ __global__ void __launch_bounds__(1024) k_bin_plan(const uint32_t* __restrict__ 
 // |record| <= vmax, |sum| <= c vmax < 2^61 2^-e, so no partial sum overflows; each record is rounded
 // once to a multiple of 2^-e (error <= 2^-e-1 = c vmax 2^-63).
 // A bin inside the block's range is added straight into the FP32 gradient (the block owns those
-// entries).  A bin cut by range boundaries is held by consecutive blocks j0..j1: each stores its
-// int64 tile in its own slot (2j for its first bin, 2j+1 for its last) and k_bin_combine adds the
-// slots in block order after the kernel ends (no cross-block synchronisation inside a kernel).
+// entries), or, in a fused training step, handed to Adam on the entries' parameters and moments.  A
+// bin cut by range boundaries is held by consecutive blocks j0..j1: each stores its int64 tile in
+// its own slot (2j for its first bin, 2j+1 for its last) and k_bin_combine adds the slots in block
+// order after the kernel ends (no cross-block synchronisation inside a kernel).  In a fused step
+// k_bin_combine also runs Adam on the entries of bins without records.
 __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceArgs a) {
   extern __shared__ unsigned long long tile64[];
   constexpr int NB = 1 << kBinBits;
@@ -1019,14 +1029,26 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
       const uint32_t base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
       const int64_t lim = min((int64_t)NB, a.n_entries - (int64_t)base);
       float2* g2 = reinterpret_cast<float2*>(a.grad_table) + base;
-      // gradient entries of an owned bin, loaded now so the loads overlap the record stream
+      float2* P2 = reinterpret_cast<float2*>(a.p) + base;
+      float2* M2 = reinterpret_cast<float2*>(a.m) + base;
+      float2* V2 = reinterpret_cast<float2*>(a.v) + base;
+      // gradient entries of an owned bin (or, fused, its parameters and moments), loaded now so the
+      // loads overlap the record stream
       constexpr int PER = NB / kReduceThreads;
-      float2 o[PER];
+      float2 o[PER], om[PER], ov[PER];
       if (!split) {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
           const int q = k * kReduceThreads + threadIdx.x;
-          if (q < lim) o[k] = g2[q];
+          if (q < lim) {
+            if (a.fused) {
+              o[k] = P2[q];
+              om[k] = M2[q];
+              ov[k] = V2[q];
+            } else {
+              o[k] = g2[q];
+            }
+          }
         }
       }
       const BinRec* __restrict__ src = a.recs + pos;
@@ -1058,9 +1080,19 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
           tile64[2 * q] = 0ull;
           tile64[2 * q + 1] = 0ull;
           if (q < lim) {
-            o[k].x += (float)((double)s0 * down);
-            o[k].y += (float)((double)s1 * down);
-            g2[q] = o[k];
+            const float d0 = (float)((double)s0 * down), d1 = (float)((double)s1 * down);
+            if (a.fused) {
+              adam_update(o[k].x, om[k].x, ov[k].x, d0, a.adam);
+              adam_update(o[k].y, om[k].y, ov[k].y, d1, a.adam);
+              P2[q] = o[k];
+              M2[q] = om[k];
+              V2[q] = ov[k];
+              if (a.th) reinterpret_cast<__half2*>(a.th)[base + q] = __floats2half2_rn(o[k].x, o[k].y);
+            } else {
+              o[k].x += d0;
+              o[k].y += d1;
+              g2[q] = o[k];
+            }
           }
         }
       } else {
@@ -1081,6 +1113,25 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
 // j0 = j - 1 .. j1 in order, and adds the result to the FP32 gradient.
 __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
   constexpr int NB = 1 << kBinBits;
+  if (a.fused) {   // bins without records: Adam with a zero gradient (dense Adam semantics)
+    for (int B = blockIdx.x; B < a.n_bins; B += gridDim.x) {
+      if (a.bin_start[B] != a.bin_start[B + 1]) continue;
+      for (int sub = 0; sub < a.n_sub; ++sub) {
+        const uint32_t base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
+        const int64_t lim = min((int64_t)NB, a.n_entries - (int64_t)base);
+        for (int q = threadIdx.x; q < lim; q += blockDim.x) {
+          float2 pp = reinterpret_cast<float2*>(a.p)[base + q], mm = reinterpret_cast<float2*>(a.m)[base + q],
+                 vv = reinterpret_cast<float2*>(a.v)[base + q];
+          adam_update(pp.x, mm.x, vv.x, 0.0f, a.adam);
+          adam_update(pp.y, mm.y, vv.y, 0.0f, a.adam);
+          reinterpret_cast<float2*>(a.p)[base + q] = pp;
+          reinterpret_cast<float2*>(a.m)[base + q] = mm;
+          reinterpret_cast<float2*>(a.v)[base + q] = vv;
+          if (a.th) reinterpret_cast<__half2*>(a.th)[base + q] = __floats2half2_rn(pp.x, pp.y);
+        }
+      }
+    }
+  }
   const uint64_t T = a.bin_start[a.n_bins];
   const uint64_t Ge = T < (uint64_t)gridDim.x ? T : (uint64_t)gridDim.x;
   const uint64_t jb = blockIdx.x;
@@ -1109,10 +1160,22 @@ __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
         s0 += (long long)S[2 * q];
         s1 += (long long)S[2 * q + 1];
       }
-      float2 o = g2[q];
-      o.x += (float)((double)s0 * down);
-      o.y += (float)((double)s1 * down);
-      g2[q] = o;
+      const float d0 = (float)((double)s0 * down), d1 = (float)((double)s1 * down);
+      if (a.fused) {
+        float2 pp = reinterpret_cast<float2*>(a.p)[base + q], mm = reinterpret_cast<float2*>(a.m)[base + q],
+               vv = reinterpret_cast<float2*>(a.v)[base + q];
+        adam_update(pp.x, mm.x, vv.x, d0, a.adam);
+        adam_update(pp.y, mm.y, vv.y, d1, a.adam);
+        reinterpret_cast<float2*>(a.p)[base + q] = pp;
+        reinterpret_cast<float2*>(a.m)[base + q] = mm;
+        reinterpret_cast<float2*>(a.v)[base + q] = vv;
+        if (a.th) reinterpret_cast<__half2*>(a.th)[base + q] = __floats2half2_rn(pp.x, pp.y);
+      } else {
+        float2 o = g2[q];
+        o.x += d0;
+        o.y += d1;
+        g2[q] = o;
+      }
     }
   }
 }
@@ -1227,9 +1290,11 @@ hipError_t launch_raysum(const float* ws, int wpr, int n_rays, float* out, hipSt
 }
 
 hipError_t launch_reduce(const float* partials, int n_blocks, int nd_pad, int nd, float* grad_dense,
-                         const float* absres, int n_rays, float inv_R, float* loss_out, hipStream_t s) {
+                         const float* absres, int n_rays, float inv_R, float* loss_out, const AdamArgs* adam,
+                         float* p, float* m, float* v, hipStream_t s) {
+  const AdamArgs A = adam ? *adam : AdamArgs{};
   k_reduce<<<(nd + 63) / 64, 1024, 0, s>>>(partials, n_blocks, nd_pad, nd, grad_dense, absres, n_rays, inv_R,
-                                          loss_out);
+                                          loss_out, adam ? 1 : 0, A, p, m, v);
   return hipGetLastError();
 }
 

@@ -249,6 +249,39 @@ def test_l1_step_matches_oracle(ora, tiny):
     assert rel(c.params(), op) <= GRAD_TOL
 
 
+def test_step_consumes_pending_gradient(ora, tiny):
+    """A training step normally runs Adam inside its reductions (the gradient is never stored); when
+    nic_backward has left a gradient pending, the step adds its own gradient to it and Adam consumes
+    the sum, as a stored-gradient optimiser would."""
+    c = tiny
+    p = random_params(ora, c.oc, 31, 1e-2)
+    c.set_params(p)
+    c.model.zero_grad()
+    c.model.tensors()[2].zero_()
+    c.model.tensors()[3].zero_()
+    t0 = c.model.get_step()
+    pix1, jit1, tp1, tj1 = _rays(c, 200, 32)
+    dA = np.random.default_rng(33).standard_normal(200).astype(np.float32)
+    c.model.backward(4, tp1, tj1, torch.tensor(dA, device="cuda"))
+    pix2, jit2, tp2, tj2 = _rays(c, 1024, 34)
+    loss = torch.zeros(1, device="cuda")
+    c.model.step(17, tp2, tj2, loss)
+    _, _, g1 = ora.ray_batch(c.oc, c.g, p, float(c.g.angles[4]), c.A[4], pix1, jit1, dA=dA)
+    ol, _, g2 = ora.ray_batch(c.oc, c.g, p, float(c.g.angles[17]), c.A[17], pix2, jit2)
+    op, om, ov = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    ora.adam(op, g1 + g2, om, ov, t0 + 1)
+    assert abs(loss.item() - ol) <= FWD_TOL * abs(ol)
+    assert rel(c.params(), op) <= GRAD_TOL
+    assert float(c.model.tensors()[1].abs().max()) == 0.0       # consumed
+    assert c.model.get_step() == t0 + 1
+    # the next step has no pending gradient again: fused form, same oracle recurrence
+    c.model.step(23, tp2, tj2, loss)
+    _, _, g3 = ora.ray_batch(c.oc, c.g, op, float(c.g.angles[23]), c.A[23], pix2, jit2)
+    ora.adam(op, g3, om, ov, t0 + 2)
+    assert rel(c.params(), op) <= GRAD_TOL
+    assert float(c.model.tensors()[1].abs().max()) == 0.0
+
+
 def test_device_draws_match_oracle(ora, tiny):
     """Pixels (Feistel over Philox, cycle walking) and jitter drawn on the GPU, bit for bit."""
     c = tiny
