@@ -21,6 +21,7 @@ constexpr int kBinBits = 12;         // reduction tile: 2^12 entries (64 KB of i
 // reduced tile by tile.
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kReduceThreads = 1024;  // threads of a bin-reduction block
+constexpr int kBinTilePer = (1 << kBinBits) / kReduceThreads;  // tile entries per thread
 
 // One corner contribution to the table gradient: entry and the two feature gradients.
 struct BinRec {

@@ -999,9 +999,81 @@ __global__ void __launch_bounds__(1024) k_bin_plan(const uint32_t* __restrict__ 
 // its own slot (2j for its first bin, 2j+1 for its last) and k_bin_combine adds the slots in block
 // order after the kernel ends (no cross-block synchronisation inside a kernel).  In a fused step
 // k_bin_combine also runs Adam on the entries of bins without records.
+// Entries of one bin tile, loaded ahead of its flush: parameters and moments (fused Adam) or the
+// gradient.  Nothing is loaded for a bin cut by a range boundary (its tile goes to a slot).
+struct TileAhead {
+  float2 o[kBinTilePer], om[kBinTilePer], ov[kBinTilePer];
+};
+
+__device__ __forceinline__ void tile_prefetch(const BinReduceArgs& a, uint32_t base, int64_t lim, bool split,
+                                              TileAhead& t) {
+  if (split) return;
+#pragma unroll
+  for (int k = 0; k < kBinTilePer; ++k) {
+    const int q = k * kReduceThreads + threadIdx.x;
+    if (q < lim) {
+      if (a.fused) {
+        t.o[k] = reinterpret_cast<const float2*>(a.p)[base + q];
+        t.om[k] = reinterpret_cast<const float2*>(a.m)[base + q];
+        t.ov[k] = reinterpret_cast<const float2*>(a.v)[base + q];
+      } else {
+        t.o[k] = reinterpret_cast<const float2*>(a.grad_table)[base + q];
+      }
+    }
+  }
+}
+
+// Moves the summed tile out (and leaves it zero): Adam on the entries (fused), added to the gradient,
+// or, for a cut bin, stored as int64 in the block's slot.  Called by all threads after a barrier.
+__device__ __forceinline__ void tile_flush(const BinReduceArgs& a, unsigned long long* tile64, uint32_t base,
+                                           int64_t lim, bool split, size_t slot, int sub, double down,
+                                           TileAhead& t) {
+  constexpr int NB = 1 << kBinBits;
+  if (split) {
+    unsigned long long* S = a.split_acc + (slot * a.n_sub + sub) * (2 * NB);
+    for (int e2 = threadIdx.x; e2 < 2 * NB; e2 += kReduceThreads) {
+      S[e2] = tile64[e2];
+      tile64[e2] = 0ull;
+    }
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < kBinTilePer; ++k) {
+    const int q = k * kReduceThreads + threadIdx.x;
+    const long long s0 = (long long)tile64[2 * q], s1 = (long long)tile64[2 * q + 1];
+    tile64[2 * q] = 0ull;
+    tile64[2 * q + 1] = 0ull;
+    if (q < lim) {
+      const float d0 = (float)((double)s0 * down), d1 = (float)((double)s1 * down);
+      if (a.fused) {
+        adam_update(t.o[k].x, t.om[k].x, t.ov[k].x, d0, a.adam);
+        adam_update(t.o[k].y, t.om[k].y, t.ov[k].y, d1, a.adam);
+        reinterpret_cast<float2*>(a.p)[base + q] = t.o[k];
+        reinterpret_cast<float2*>(a.m)[base + q] = t.om[k];
+        reinterpret_cast<float2*>(a.v)[base + q] = t.ov[k];
+        if (a.th) reinterpret_cast<__half2*>(a.th)[base + q] = __floats2half2_rn(t.o[k].x, t.o[k].y);
+      } else {
+        t.o[k].x += d0;
+        t.o[k].y += d1;
+        reinterpret_cast<float2*>(a.grad_table)[base + q] = t.o[k];
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void rec_add(unsigned long long* tile64, const BinRec& r, uint32_t base, double up) {
+  const uint32_t q = r.idx - base;   // wraps above NB for records of another tile
+  if (q < (uint32_t)(1 << kBinBits)) {
+    atomicAdd(tile64 + 2 * q, (unsigned long long)__double2ll_rn((double)r.v0 * up));
+    atomicAdd(tile64 + 2 * q + 1, (unsigned long long)__double2ll_rn((double)r.v1 * up));
+  }
+}
+
 __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceArgs a) {
   extern __shared__ unsigned long long tile64[];
+  __shared__ uint32_t sb[65];                                      // bin starts of the block's first bins
   constexpr int NB = 1 << kBinBits;
+  constexpr int U = 4, CH = U * kReduceThreads;                    // records per thread / block per chunk
   const uint64_t T = a.bin_start[a.n_bins];
   const uint64_t Ge = T < (uint64_t)gridDim.x ? T : (uint64_t)gridDim.x;
   const uint64_t jb = blockIdx.x;
@@ -1010,51 +1082,88 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
   const float vmax = __uint_as_float(*a.rec_max_bits);
   int ev;
   frexpf(vmax, &ev);                                               // vmax < 2^ev
-  const int n_sub = a.n_sub;
-  for (int e2 = threadIdx.x; e2 < 2 * NB; e2 += blockDim.x) tile64[e2] = 0ull;
-  __syncthreads();
   const int first_bin = a.block_first_bin[jb];
-  uint32_t pos = rs;
-  for (int B = first_bin; pos < re; ++B) {
-    const uint32_t b_start = a.bin_start[B], b_end = a.bin_start[B + 1];
-    if (b_end <= pos) continue;                                    // empty bin
-    const uint32_t seg_end = min(re, b_end);
-    const bool split = b_start < rs || b_end > re;
+  if (threadIdx.x < 65 && first_bin + (int)threadIdx.x <= a.n_bins) sb[threadIdx.x] = a.bin_start[first_bin + threadIdx.x];
+  for (int e2 = threadIdx.x; e2 < 2 * NB; e2 += kReduceThreads) tile64[e2] = 0ull;
+  __syncthreads();
+  auto bstart = [&](int B) -> uint32_t { return B - first_bin < 65 ? sb[B - first_bin] : a.bin_start[B]; };
+
+  // current segment: the part of bin B inside [rs, re)
+  int B = first_bin;
+  uint32_t b_start = bstart(B), b_end = bstart(B + 1);
+  uint32_t seg_end, base;
+  int64_t lim;
+  bool split;
+  double up, down;
+  TileAhead ta;
+  auto begin_segment = [&](int sub) {
+    seg_end = min(re, b_end);
+    split = b_start < rs || b_end > re;
     int ec;
     frexpf((float)(b_end - b_start) + 1.0f, &ec);                  // count < 2^ec
     const int e = 61 - ev - ec;
-    const double up = ldexp(1.0, e), down = ldexp(1.0, -e);
-    const size_t slot = 2 * (size_t)jb + (B == first_bin ? 0 : 1);
-    for (int sub = 0; sub < n_sub; ++sub) {
-      const uint32_t base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
-      const int64_t lim = min((int64_t)NB, a.n_entries - (int64_t)base);
-      float2* g2 = reinterpret_cast<float2*>(a.grad_table) + base;
-      float2* P2 = reinterpret_cast<float2*>(a.p) + base;
-      float2* M2 = reinterpret_cast<float2*>(a.m) + base;
-      float2* V2 = reinterpret_cast<float2*>(a.v) + base;
-      // gradient entries of an owned bin (or, fused, its parameters and moments), loaded now so the
-      // loads overlap the record stream
-      constexpr int PER = NB / kReduceThreads;
-      float2 o[PER], om[PER], ov[PER];
-      if (!split) {
+    up = ldexp(1.0, e);
+    down = ldexp(1.0, -e);
+    base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
+    lim = min((int64_t)NB, a.n_entries - (int64_t)base);
+    tile_prefetch(a, base, lim, split, ta);
+  };
+
+  if (a.n_sub == 1) {
+    // One continuous stream over [rs, re) in chunks of CH records, the next chunk's loads in flight
+    // while the current one is added; a segment ends (barrier, flush, barrier) wherever its bin ends.
+    begin_segment(0);
+    BinRec cur[U], nxt[U];
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-          const int q = k * kReduceThreads + threadIdx.x;
-          if (q < lim) {
-            if (a.fused) {
-              o[k] = P2[q];
-              om[k] = M2[q];
-              ov[k] = V2[q];
-            } else {
-              o[k] = g2[q];
-            }
-          }
+    for (int k = 0; k < U; ++k) {
+      const uint32_t r = rs + k * kReduceThreads + threadIdx.x;
+      if (r < re) cur[k] = a.recs[r];
+    }
+    for (uint32_t cb = rs; cb < re; cb += CH) {
+      const uint32_t ce = min(re, cb + CH);
+      if (ce < re) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const uint32_t r = ce + k * kReduceThreads + threadIdx.x;
+          if (r < re) nxt[k] = a.recs[r];
         }
       }
+      uint32_t lo = cb;
+      for (;;) {
+        const uint32_t hi = min(seg_end, ce);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const uint32_t r = cb + k * kReduceThreads + threadIdx.x;
+          if (r >= lo && r < hi) rec_add(tile64, cur[k], base, up);
+        }
+        if (seg_end > ce) break;                                   // the segment goes on in the next chunk
+        __syncthreads();
+        tile_flush(a, tile64, base, lim, split, 2 * (size_t)jb + (B == first_bin ? 0 : 1), 0, down, ta);
+        __syncthreads();
+        if (seg_end >= re) break;                                  // the block's range is done
+        lo = seg_end;
+        do {                                                       // next bin with records
+          ++B;
+          b_start = b_end;
+          b_end = bstart(B + 1);
+        } while (b_end <= b_start);
+        begin_segment(0);
+        if (lo >= ce) break;
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) cur[k] = nxt[k];
+    }
+    return;
+  }
+
+  // Bins of several tiles: each segment is streamed once per tile.
+  uint32_t pos = rs;
+  for (;;) {
+    for (int sub = 0; sub < a.n_sub; ++sub) {
+      begin_segment(sub);
       const BinRec* __restrict__ src = a.recs + pos;
       const int cnt = (int)(seg_end - pos);
-      constexpr int U = 8;       // records in flight per thread; lane-contiguous (coalesced) loads
-      for (int r0 = 0; r0 < cnt; r0 += kReduceThreads * U) {
+      for (int r0 = 0; r0 < cnt; r0 += CH) {
         BinRec rc[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -1062,49 +1171,20 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
           if (r < cnt) rc[k] = src[r];
         }
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-          const int r = r0 + k * kReduceThreads + threadIdx.x;
-          const uint32_t q = rc[k].idx - base;   // wraps above NB for records of another tile
-          if (r < cnt && q < (uint32_t)NB) {
-            atomicAdd(tile64 + 2 * q, (unsigned long long)__double2ll_rn((double)rc[k].v0 * up));
-            atomicAdd(tile64 + 2 * q + 1, (unsigned long long)__double2ll_rn((double)rc[k].v1 * up));
-          }
-        }
+        for (int k = 0; k < U; ++k)
+          if (r0 + k * kReduceThreads + (int)threadIdx.x < cnt) rec_add(tile64, rc[k], base, up);
       }
       __syncthreads();
-      if (!split) {
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-          const int q = k * kReduceThreads + threadIdx.x;
-          const long long s0 = (long long)tile64[2 * q], s1 = (long long)tile64[2 * q + 1];
-          tile64[2 * q] = 0ull;
-          tile64[2 * q + 1] = 0ull;
-          if (q < lim) {
-            const float d0 = (float)((double)s0 * down), d1 = (float)((double)s1 * down);
-            if (a.fused) {
-              adam_update(o[k].x, om[k].x, ov[k].x, d0, a.adam);
-              adam_update(o[k].y, om[k].y, ov[k].y, d1, a.adam);
-              P2[q] = o[k];
-              M2[q] = om[k];
-              V2[q] = ov[k];
-              if (a.th) reinterpret_cast<__half2*>(a.th)[base + q] = __floats2half2_rn(o[k].x, o[k].y);
-            } else {
-              o[k].x += d0;
-              o[k].y += d1;
-              g2[q] = o[k];
-            }
-          }
-        }
-      } else {
-        unsigned long long* S = a.split_acc + (slot * n_sub + sub) * (2 * NB);
-        for (int e2 = threadIdx.x; e2 < 2 * NB; e2 += kReduceThreads) {
-          S[e2] = tile64[e2];
-          tile64[e2] = 0ull;
-        }
-      }
+      tile_flush(a, tile64, base, lim, split, 2 * (size_t)jb + (B == first_bin ? 0 : 1), sub, down, ta);
       __syncthreads();
     }
     pos = seg_end;
+    if (pos >= re) break;
+    do {
+      ++B;
+      b_start = b_end;
+      b_end = bstart(B + 1);
+    } while (b_end <= b_start);
   }
 }
 
