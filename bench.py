@@ -78,7 +78,7 @@ def algorithmic_bytes(cfg, lay, n_points, fused_adam=False):
     }
 
 
-def cpu_baseline(w, g, A, n_rays_sample=384):
+def cpu_baseline(w, g, A, n_rays_sample=1024):
     """FP64 oracle (single thread) on a bounded sample: n_rays_sample rays of one view forward +
     backward, plus one dense Adam over all parameters; scaled to the full step of R rays."""
     import oracle as ora
