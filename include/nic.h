@@ -241,6 +241,15 @@ nic_status nic_load_state(nic_model* m, const void* buf, size_t bytes);
  * squared errors are summed in FP64 on the device; synchronous.  +inf when pred == gt. */
 nic_status nic_psnr(nic_model* m, const float* gt_dev, const float* pred_dev, int64_t n, double* psnr_host);
 
+/* 3-D SSIM (the structural similarity of Wang et al. 2004, which Sec. 3.1 uses with PSNR, taken
+ * over volumes): local means, variances and covariance under a separable Gaussian window (sigma 1.5,
+ * 11 taps per axis, weights summing to 1), C1 = (0.01 L)^2 and C2 = (0.03 L)^2 with L = max(gt), the
+ * SSIM map averaged over the voxels whose whole window lies inside the volume.  gt_dev, pred_dev:
+ * device float32 [dims[2]][dims[1]][dims[0]], every dim in [11, 4096].  FP64 on the device;
+ * synchronous. */
+nic_status nic_ssim(nic_model* m, const float* gt_dev, const float* pred_dev, const int32_t dims[3],
+                    double* ssim_host);
+
 /* Current Adam step count (host only). */
 int64_t nic_get_step(const nic_model* m);
 

@@ -75,6 +75,8 @@ def lib():
         L.ora_encode.argtypes = [P(Cfg), d, f, C.c_int64, d, u32, d]
         L.ora_field.argtypes = [P(Cfg), d, f, C.c_int64, d, d, d]
         L.ora_field_from_features.argtypes = [P(Cfg), d, d, C.c_int64, d]
+        L.ora_ssim.argtypes = [d, d, C.c_int32, C.c_int32, C.c_int32]
+        L.ora_ssim.restype = C.c_double
         L.ora_field_backward.argtypes = [P(Cfg), d, f, C.c_int64, d, d]
         L.ora_ray_samples.argtypes = [P(Geom), C.c_double, C.c_int32, C.c_int32, f, f, d]
         L.ora_ray_samples.restype = C.c_int
@@ -242,6 +244,14 @@ def field_from_features(cfg: Config, params, enc):
     lib().ora_field_from_features(C.byref(cfg.c()), _p(params, C.c_double), _p(enc, C.c_double),
                                   enc.shape[0], _p(mu, C.c_double))
     return mu
+
+
+def ssim(gt, pred) -> float:
+    """3-D SSIM of two [nz][ny][nx] volumes (Gaussian window sigma 1.5, 11 taps; L = max(gt))."""
+    gt = _c64(gt)
+    pred = _c64(pred)
+    nz, ny, nx = gt.shape
+    return float(lib().ora_ssim(_p(gt, C.c_double), _p(pred, C.c_double), nx, ny, nz))
 
 
 def field_backward(cfg: Config, params, xn, dmu):

@@ -715,6 +715,43 @@ double ora_psnr(const double* gt, const double* pred, int64_t n) {
   return 10.0 * log10(mx * mx / mse);
 }
 
+/* 3-D SSIM (Wang et al. 2004, the image-quality measure of Sec. 3.1, over volumes [nz][ny][nx]):
+ * Gaussian window with sigma 1.5 and 11 taps per axis, normalised; C1 = (0.01 L)^2, C2 = (0.03 L)^2,
+ * L = max(gt); mean of the SSIM map over voxels whose window lies inside the volume.  Returns NAN
+ * when a dimension is below 11. */
+double ora_ssim(const double* gt, const double* pred, int32_t nx, int32_t ny, int32_t nz) {
+  const int R = 5;
+  if (nx < 2 * R + 1 || ny < 2 * R + 1 || nz < 2 * R + 1) return NAN;
+  double w[11], s = 0.0;
+  for (int i = -R; i <= R; ++i) s += exp(-(double)(i * i) / (2.0 * 1.5 * 1.5));
+  for (int i = -R; i <= R; ++i) w[i + R] = exp(-(double)(i * i) / (2.0 * 1.5 * 1.5)) / s;
+  double L = -INFINITY;
+  for (int64_t i = 0; i < (int64_t)nx * ny * nz; ++i) if (gt[i] > L) L = gt[i];
+  const double c1 = (0.01 * L) * (0.01 * L), c2 = (0.03 * L) * (0.03 * L);
+  double total = 0.0;
+  int64_t count = 0;
+  for (int z = R; z < nz - R; ++z)
+    for (int y = R; y < ny - R; ++y)
+      for (int x = R; x < nx - R; ++x) {
+        double ma = 0.0, mb = 0.0, maa = 0.0, mbb = 0.0, mab = 0.0;
+        for (int dz = -R; dz <= R; ++dz)
+          for (int dy = -R; dy <= R; ++dy)
+            for (int dx = -R; dx <= R; ++dx) {
+              const double ww = w[dz + R] * w[dy + R] * w[dx + R];
+              const int64_t i = ((int64_t)(z + dz) * ny + (y + dy)) * nx + (x + dx);
+              ma += ww * gt[i];
+              mb += ww * pred[i];
+              maa += ww * gt[i] * gt[i];
+              mbb += ww * pred[i] * pred[i];
+              mab += ww * gt[i] * pred[i];
+            }
+        const double va = maa - ma * ma, vb = mbb - mb * mb, cab = mab - ma * mb;
+        total += ((2.0 * ma * mb + c1) * (2.0 * cab + c2)) / ((ma * ma + mb * mb + c1) * (va + vb + c2));
+        ++count;
+      }
+  return total / (double)count;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Pre-training for Mapping Consistency Initialization (Sec. 2.1, Sec. 2.4, Eq. 2)             */
 /* ------------------------------------------------------------------------------------------ */

@@ -992,4 +992,30 @@ nic_status nic_psnr(nic_model* m, const float* gt_dev, const float* pred_dev, in
   return NIC_OK;
 }
 
+nic_status nic_ssim(nic_model* m, const float* gt_dev, const float* pred_dev, const int32_t dims[3],
+                    double* ssim_host) {
+  if (!model_ok(m) || !gt_dev || !pred_dev || !dims || !ssim_host) return fail(NIC_EINVAL, "NULL argument");
+  for (int k = 0; k < 3; ++k)
+    if (dims[k] < 11 || dims[k] > 4096) return fail(NIC_EINVAL, "dims must be in [11, 4096] (11-voxel window)");
+  const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
+  const int64_t nv = (int64_t)(dims[0] - 10) * (dims[1] - 10) * (dims[2] - 10);
+  // data range L = max(gt), from the PSNR kernel's per-block maxima
+  const int nbm = (int)std::min<int64_t>(kSqerrBlocks, (n + 255) / 256);
+  NIC_HIP(launch_sqerr(gt_dev, gt_dev, n, m->sqerr, nbm, m->stream));
+  std::vector<double> h(2 * (size_t)kSqerrBlocks);
+  NIC_HIP(hipMemcpyAsync(h.data(), m->sqerr, 2 * (size_t)nbm * 8, hipMemcpyDeviceToHost, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  double L = -1e300;
+  for (int b = 0; b < nbm; ++b) L = std::max(L, h[2 * b + 1]);
+  const double c1 = (0.01 * L) * (0.01 * L), c2 = (0.03 * L) * (0.03 * L);
+  const int nb = (int)std::min<int64_t>(2 * kSqerrBlocks, (nv + 255) / 256);
+  NIC_HIP(launch_ssim(gt_dev, pred_dev, dims[0], dims[1], dims[2], c1, c2, m->sqerr, nb, m->stream));
+  NIC_HIP(hipMemcpyAsync(h.data(), m->sqerr, (size_t)nb * 8, hipMemcpyDeviceToHost, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  double total = 0.0;
+  for (int b = 0; b < nb; ++b) total += h[b];
+  *ssim_host = total / (double)nv;
+  return NIC_OK;
+}
+
 }  // extern "C"

@@ -137,6 +137,8 @@ struct BinReduceArgs {
 hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s);
 size_t bin_reduce_lds();
 const void* bin_reduce_kernel();
+hipError_t launch_ssim(const float* gt, const float* pred, int nx, int ny, int nz, double c1, double c2,
+                       double* partials, int n_blocks, hipStream_t s);
 hipError_t launch_sqerr(const float* gt, const float* pred, int64_t n, double* partials, int n_blocks,
                         hipStream_t s);
 hipError_t launch_encode(const LevelTab& lt, const void* table, int half_table, const float* xn, int64_t n,

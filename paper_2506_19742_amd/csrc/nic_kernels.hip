@@ -1288,6 +1288,57 @@ __global__ void __launch_bounds__(256) k_sqerr(const float* __restrict__ gt, con
   }
 }
 
+// 3-D SSIM (Wang et al. 2004 extended to volumes): local statistics under a separable Gaussian
+// window (sigma 1.5, radius 5, weights normalised to sum 1), C1 = (0.01 L)^2, C2 = (0.03 L)^2, over
+// the voxels whose whole window lies inside the volume; FP64 throughout.  Grid-stride over those
+// voxels; partials[b] = the block's sum of SSIM terms (fixed order: per thread, then a tree).
+__global__ void __launch_bounds__(256) k_ssim(const float* __restrict__ gt, const float* __restrict__ pred,
+                                              int nx, int ny, int nz, double c1, double c2,
+                                              double* __restrict__ partials) {
+  constexpr int R = 5;
+  __shared__ double w[2 * R + 1];
+  __shared__ double red[256];
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = -R; i <= R; ++i) s += exp(-(double)(i * i) / (2.0 * 1.5 * 1.5));
+    for (int i = -R; i <= R; ++i) w[i + R] = exp(-(double)(i * i) / (2.0 * 1.5 * 1.5)) / s;
+  }
+  __syncthreads();
+  const int vx = nx - 2 * R, vy = ny - 2 * R, vz = nz - 2 * R;
+  const int64_t nv = (int64_t)vx * vy * vz;
+  double term = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv; q += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(q % vx) + R;
+    const int y = (int)((q / vx) % vy) + R;
+    const int z = (int)(q / ((int64_t)vx * vy)) + R;
+    double sa = 0.0, sb = 0.0, saa = 0.0, sbb = 0.0, sab = 0.0;
+    for (int dz = -R; dz <= R; ++dz) {
+      for (int dy = -R; dy <= R; ++dy) {
+        const double wzy = w[dz + R] * w[dy + R];
+        const int64_t row = ((int64_t)(z + dz) * ny + (y + dy)) * nx;
+        for (int dx = -R; dx <= R; ++dx) {
+          const double ww = wzy * w[dx + R];
+          const double a = gt[row + x + dx], b = pred[row + x + dx];
+          sa += ww * a;
+          sb += ww * b;
+          saa += ww * a * a;
+          sbb += ww * b * b;
+          sab += ww * a * b;
+        }
+      }
+    }
+    const double va = saa - sa * sa, vb = sbb - sb * sb, cab = sab - sa * sb;
+    term += ((2.0 * sa * sb + c1) * (2.0 * cab + c2)) / ((sa * sa + sb * sb + c1) * (va + vb + c2));
+  }
+  red[threadIdx.x] = term;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
 // Raw encoding of n points (all levels, natural channel order) and optional corner entries.
 __global__ void k_encode(const LevelTab lt, const void* __restrict__ table, int half_table,
                          const float* __restrict__ xn, int64_t n, float* __restrict__ enc,
@@ -1435,6 +1486,12 @@ hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s) {
 }
 
 const void* bin_reduce_kernel() { return reinterpret_cast<const void*>(&k_bin_reduce); }
+
+hipError_t launch_ssim(const float* gt, const float* pred, int nx, int ny, int nz, double c1, double c2,
+                       double* partials, int n_blocks, hipStream_t s) {
+  k_ssim<<<n_blocks, 256, 0, s>>>(gt, pred, nx, ny, nz, c1, c2, partials);
+  return hipGetLastError();
+}
 
 hipError_t launch_sqerr(const float* gt, const float* pred, int64_t n, double* partials, int n_blocks,
                         hipStream_t s) {

@@ -74,7 +74,8 @@ def reconstruct(cfg: nic.Config, g, A, gt, n_steps: int, eval_every: int = 100, 
             hit = (done, t_train)
             if stop_at_target:
                 break
-    return {"curve": curve, "hit": hit, "model": m, "proj": proj}
+    final_ssim = m.ssim(gtd, m.render_volume(n, n, n))
+    return {"curve": curve, "hit": hit, "model": m, "proj": proj, "ssim": final_ssim}
 
 
 def render_table(m, n: int):
@@ -134,8 +135,9 @@ def stability(cfg: nic.Config, g, A, gt, n_steps: int, every: int, n_probe: int,
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--stage", choices=["calibrate", "pretrain", "pretrain_gt", "heldout", "stability"],
+    ap.add_argument("--stage", choices=["calibrate", "pretrain", "pretrain_gt", "heldout", "stability", "views"],
                     required=True)
+    ap.add_argument("--views", default="10,20,30,50,100")
     ap.add_argument("--out", default="gpurun_out/mci")
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--depth", type=int, default=4)
@@ -199,6 +201,27 @@ def main(argv=None):
         json.dump(res, open(f"{args.out}/stability{args.tag}.json", "w"))
         return
 
+    if args.stage == "views":
+        # Fig. 7 analogue: final PSNR and SSIM against the number of views
+        res = {}
+        for V in [int(v) for v in args.views.split(",")]:
+            for i in range(args.n_heldout):
+                seed = args.seed_base + i
+                ph, g, A, gt = scan_workload(256, 20, seed, V, 256, 1e5)
+                for arm in args.arms.split(","):
+                    parts = arm.split("_")
+                    prec = 1 if parts[0] == "bf16" else 0
+                    use = None if parts[1] == "random" else open(f"{args.out}/mci_blob.bin", "rb").read()
+                    r = reconstruct(cfg_for(prec, 3000 + i), g, A, gt, args.steps, args.eval_every, args.target,
+                                    blob=use)
+                    r["model"].close()
+                    p = r["curve"][-1][2]
+                    log(f"views {V:4d} phantom {seed} {arm}: PSNR {p:.2f} dB, SSIM {r['ssim']:.4f}, hit {r['hit']}")
+                    res.setdefault(arm, {}).setdefault(str(V), {})[seed] = {"psnr": p, "ssim": r["ssim"],
+                                                                         "hit": r["hit"]}
+                json.dump(res, open(f"{args.out}/views{args.tag}.json", "w"))
+        return
+
     if args.stage == "pretrain_gt":
         ph = synth.make_phantom(args.gt_seed, 20)
         vol = synth.voxelize(ph, args.gt_grid).astype(np.float32)[None]
@@ -227,7 +250,7 @@ def main(argv=None):
             r["model"].close()
             best = max(p for _, _, p in r["curve"])
             log(f"  -> hit {r['hit']}, best {best:.2f} dB")
-            results.setdefault(arm, {})[seed] = {"curve": r["curve"], "hit": r["hit"]}
+            results.setdefault(arm, {})[seed] = {"curve": r["curve"], "hit": r["hit"], "ssim": r["ssim"]}
         json.dump(results, open(f"{args.out}/heldout{args.tag}.json", "w"))
 
 

@@ -60,7 +60,7 @@ EXPORTS = ["nic_describe", "nic_workspace_size", "nic_create", "nic_destroy", "n
            "nic_adam", "nic_zero_grad", "nic_query", "nic_render_volume", "nic_encode",
            "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step",
            "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr",
-           "nic_save_state", "nic_load_state", "nic_field_from_features"]
+           "nic_save_state", "nic_load_state", "nic_field_from_features", "nic_ssim"]
 
 _lib = None
 
@@ -106,6 +106,7 @@ def lib():
             "nic_save_state": ([vp, vp, P(C.c_size_t)], C.c_int32),
             "nic_load_state": ([vp, vp, C.c_size_t], C.c_int32),
             "nic_field_from_features": ([vp, vp, C.c_int64, vp], C.c_int32),
+            "nic_ssim": ([vp, vp, vp, P(C.c_int32), P(C.c_double)], C.c_int32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -381,6 +382,17 @@ class Model:
     def psnr(self, gt, pred) -> float:
         out = C.c_double()
         _check(lib().nic_psnr(self.h, _ptr(gt), _ptr(pred), gt.numel(), C.byref(out)))
+        return float(out.value)
+
+    def ssim(self, gt, pred) -> float:
+        """3-D SSIM of two [nz][ny][nx] float32 device volumes (Gaussian window, see nic_ssim)."""
+        torch = self.torch
+        if gt.shape != pred.shape or gt.dim() != 3 or gt.dtype != torch.float32 or pred.dtype != torch.float32 \
+                or not gt.is_contiguous() or not pred.is_contiguous():
+            raise ValueError("gt and pred must be contiguous float32 volumes of the same [nz][ny][nx] shape")
+        dims = (C.c_int32 * 3)(gt.shape[2], gt.shape[1], gt.shape[0])
+        out = C.c_double()
+        _check(lib().nic_ssim(self.h, _ptr(gt), _ptr(pred), dims, C.byref(out)))
         return float(out.value)
 
     # --- parameter helpers ------------------------------------------------------------------------

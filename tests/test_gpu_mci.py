@@ -168,6 +168,21 @@ def test_mlp_blob_roundtrip_and_transfer(ora):
         mm.close()
 
 
+def test_ssim_matches_oracle(ora):
+    cfg, oc, m = _model(ora, 1)
+    rng = np.random.default_rng(65)
+    z, y, x = np.meshgrid(np.arange(21), np.arange(18), np.arange(25), indexing="ij")
+    gt = (0.02 + 0.01 * np.sin(x / 3.0) * np.cos(y / 5.0) + 0.004 * z / 21).astype(np.float32)
+    pred = (gt + 2e-3 * rng.standard_normal(gt.shape)).astype(np.float32)
+    tg, tp = torch.tensor(gt, device="cuda"), torch.tensor(pred, device="cuda")
+    v = m.ssim(tg, tp)
+    assert abs(v - ora.ssim(gt, pred)) <= 1e-12
+    assert abs(m.ssim(tg, tg) - 1.0) <= 1e-12
+    with pytest.raises(nic.NicError):
+        m.ssim(tg[:, :8].contiguous(), tp[:, :8].contiguous())
+    m.close()
+
+
 def test_psnr_matches_oracle(ora):
     cfg, oc, m = _model(ora, 1)
     rng = np.random.default_rng(64)

@@ -665,3 +665,35 @@ def test_field_from_features_pins(ora, layernorm):
         assert np.allclose(shifted, mu, rtol=1e-12, atol=1e-15)
     else:
         assert np.abs(shifted - mu).max() > 1e-6
+
+
+def _ssim_scipy(gt, pred):
+    """3-D SSIM through scipy.ndimage.gaussian_filter (sigma 1.5, radius 5), cropped to the voxels
+    whose window lies inside the volume: an independent implementation of the filtering."""
+    from scipy.ndimage import gaussian_filter
+    f = lambda v: gaussian_filter(v, sigma=1.5, truncate=5.0 / 1.5, mode="constant")[5:-5, 5:-5, 5:-5]
+    L = gt.max()
+    c1, c2 = (0.01 * L) ** 2, (0.03 * L) ** 2
+    ma, mb = f(gt), f(pred)
+    va, vb, cab = f(gt * gt) - ma * ma, f(pred * pred) - mb * mb, f(gt * pred) - ma * mb
+    return float(np.mean((2 * ma * mb + c1) * (2 * cab + c2) / ((ma * ma + mb * mb + c1) * (va + vb + c2))))
+
+
+def test_ssim_pins(ora):
+    """SSIM (Wang et al. 2004, named in Sec. 3.1) over volumes: 1 for identical volumes, symmetric, and
+    equal to a scipy gaussian_filter computation of the same definition."""
+    rng = np.random.default_rng(81)
+    z, y, x = np.meshgrid(np.arange(14), np.arange(17), np.arange(20), indexing="ij")
+    gt = 0.02 + 0.01 * np.sin(x / 3.0) * np.cos(y / 4.0) + 0.005 * z / 14 + 0.002 * rng.random(x.shape)
+    pred = gt + 0.003 * rng.standard_normal(gt.shape)
+    assert ora.ssim(gt, gt) == pytest.approx(1.0, abs=1e-12)
+    s = ora.ssim(gt, pred)
+    assert 0.0 < s < 1.0
+    assert s == pytest.approx(_ssim_scipy(gt, pred), rel=1e-10)
+    # symmetric in everything but L = max(gt): with equal maxima the two orders agree
+    p2 = pred.copy()
+    p2[0, 0, 0] = gt.max() + 1.0
+    g2 = gt.copy()
+    g2[0, 0, 0] = gt.max() + 1.0
+    assert ora.ssim(g2, p2) == pytest.approx(ora.ssim(p2, g2), rel=1e-12)
+    assert np.isnan(ora.ssim(gt[:10], pred[:10]))
