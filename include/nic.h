@@ -187,6 +187,21 @@ nic_status nic_zero_grad(nic_model* m);
  * (device float32 [n]). */
 nic_status nic_query(nic_model* m, const float* xn_dev, int64_t n, float* mu_dev);
 
+/* Channel mask (Sec. 2.3: channels of the hash features that carry only noise, found with an FFT,
+ * are masked during training): from this call on, every forward and backward pass feeds
+ * mask_host[c] * (channel c of the encoding) to LayerNorm, c = level * 2 + feature; the table
+ * entries of a channel with mask 0 receive no gradient.  mask_host: host float32 [n], n must be
+ * n_levels * 2; copied.  NULL removes the mask.  Not part of saved states or MLP blobs. */
+nic_status nic_set_channel_mask(nic_model* m, const float* mask_host, int32_t n);
+
+/* Spectral noise measure of every hash-feature channel, the FFT criterion behind the channel mask
+ * (Sec. 2.3): for level l of resolution N, the channel's field at the G^3 vertices v0 + i,
+ * G = min(g_max, N), v0 = (N - G) / 2 (centre of the box), from the FP32 table of the first hash
+ * table; 3-D DFT in FP64; hf_host[2l + f] (host float32 [n_levels * 2]) = power with
+ * max_d |k_d| > G/4 over all non-DC power (about 0.875 for white noise, near 0 for a smooth field).
+ * g_max in [4, 64]; uses the record buffer as scratch; synchronous. */
+nic_status nic_channel_spectrum(nic_model* m, int32_t g_max, float* hf_host);
+
 /* The feature-to-attenuation mapping alone (Sec. 2.3; Fig. 3 studies how it drifts for fixed
  * features during training): LayerNorm (when enabled), MLP and output activation applied to n given
  * encoder outputs enc_dev (device float32 [n][n_levels * 2], channel l * 2 + f, the layout

@@ -36,7 +36,8 @@ class Cfg(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("feats", C.c_int32), ("log2_table", C.c_int32),
                 ("base_res", C.c_int32), ("max_res", C.c_int32), ("depth", C.c_int32),
                 ("width", C.c_int32), ("out_act", C.c_int32), ("layernorm", C.c_int32),
-                ("pad_", C.c_int32), ("mu_max", C.c_double), ("ln_eps", C.c_double)]
+                ("masked", C.c_int32), ("mu_max", C.c_double), ("ln_eps", C.c_double),
+                ("mask", C.c_double * 64)]
 
 
 class Geom(C.Structure):
@@ -130,11 +131,13 @@ class Config:
     layernorm: int = 1
     mu_max: float = 0.25
     ln_eps: float = 1e-5
+    mask: tuple = ()          # per-channel mask before LayerNorm (Sec. 2.3); empty = none
 
     def c(self) -> Cfg:
+        m = (C.c_double * 64)(*([float(v) for v in self.mask] + [1.0] * (64 - len(self.mask))))
         return Cfg(self.n_levels, self.feats, self.log2_table, self.base_res, self.max_res,
-                   self.depth, self.width, self.out_act, self.layernorm, 0, self.mu_max,
-                   self.ln_eps)
+                   self.depth, self.width, self.out_act, self.layernorm, 1 if len(self.mask) else 0,
+                   self.mu_max, self.ln_eps, m)
 
 
 def geom_struct(g) -> Geom:
@@ -244,6 +247,34 @@ def field_from_features(cfg: Config, params, enc):
     lib().ora_field_from_features(C.byref(cfg.c()), _p(params, C.c_double), _p(enc, C.c_double),
                                   enc.shape[0], _p(mu, C.c_double))
     return mu
+
+
+def channel_hf_fraction(cfg: Config, table, g_max: int = 64) -> np.ndarray:
+    """FFT noise measure of every encoder channel (Sec. 2.3 masks channels found noisy with an FFT):
+    for level l of resolution N, the channel's field at the G^3 vertices v0 + i of that level
+    (G = min(g_max, N), v0 = (N - G) // 2, points (v0 + i) / N in FP32), numpy's 3-D FFT, and the
+    power with max_d |k_d| > G/4 (signed frequencies) over all non-DC power."""
+    res, dense, off, size, n = levels(cfg)
+    out = np.zeros(cfg.n_levels * cfg.feats)
+    for l in range(cfg.n_levels):
+        N = int(res[l])
+        G = min(g_max, N)
+        v0 = (N - G) // 2
+        iz, iy, ix = np.meshgrid(np.arange(G), np.arange(G), np.arange(G), indexing="ij")
+        pts = np.stack([(np.float32(v0) + ix.astype(np.float32)) / np.float32(N),
+                        (np.float32(v0) + iy.astype(np.float32)) / np.float32(N),
+                        (np.float32(v0) + iz.astype(np.float32)) / np.float32(N)], -1).reshape(-1, 3)
+        enc = encode(cfg, table, pts.astype(np.float32))
+        f = np.fft.fftfreq(G) * G
+        kz, ky, kx = np.meshgrid(np.abs(f), np.abs(f), np.abs(f), indexing="ij")
+        high = np.maximum(np.maximum(kx, ky), kz) * 4 > G
+        for c in range(cfg.feats):
+            ch = l * cfg.feats + c
+            P = np.abs(np.fft.fftn(enc[:, ch].reshape(G, G, G))) ** 2
+            P[0, 0, 0] = 0.0
+            tot = P.sum()
+            out[ch] = P[high].sum() / tot if tot > 0 else 0.0
+    return out
 
 
 def ssim(gt, pred) -> float:

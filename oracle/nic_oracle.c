@@ -56,9 +56,10 @@ typedef struct {
   int32_t width;           /* W */
   int32_t out_act;         /* 0: mu_max*sigmoid, 1: identity, 2: softplus */
   int32_t layernorm;       /* 1: LayerNorm between encoder and network */
-  int32_t pad_;
+  int32_t masked;          /* 1: the encoder's channels are multiplied by mask[] before LayerNorm */
   double mu_max;
   double ln_eps;
+  double mask[64];         /* channel mask (Sec. 2.3: noisy channels are masked), used when masked */
 } ora_cfg;
 
 typedef struct {
@@ -381,23 +382,26 @@ static void point_forward(const ora_cfg* c, const ora_layout* o, const double* t
 
 /* From the encoder output st->enc to mu: LayerNorm (Sec. 2.3), hidden layers, head, activation. */
 static void features_forward(const ora_cfg* c, const ora_layout* o, const double* d, point_state* st) {
+  /* Channel mask (Sec. 2.3): the network sees mask[i] * enc[i]; st->enc keeps the raw encoding. */
+  double e[ORA_MAX_C];
+  for (int i = 0; i < o->C; ++i) e[i] = c->masked ? c->mask[i] * st->enc[i] : st->enc[i];
   /* LayerNorm over the C channels of this point: biased variance, then gain and bias. */
   if (c->layernorm) {
     double m = 0.0;
-    for (int i = 0; i < o->C; ++i) m += st->enc[i];
+    for (int i = 0; i < o->C; ++i) m += e[i];
     m /= (double)o->C;
     double v = 0.0;
-    for (int i = 0; i < o->C; ++i) v += (st->enc[i] - m) * (st->enc[i] - m);
+    for (int i = 0; i < o->C; ++i) v += (e[i] - m) * (e[i] - m);
     v /= (double)o->C;
     double s = 1.0 / sqrt(v + c->ln_eps);
     st->mean = m; st->rstd = s;
     for (int i = 0; i < o->C; ++i) {
-      st->xhat[i] = (st->enc[i] - m) * s;
+      st->xhat[i] = (e[i] - m) * s;
       st->z[i] = d[o->o_lng + i] * st->xhat[i] + d[o->o_lnb + i];
     }
   } else {
     st->mean = 0.0; st->rstd = 1.0;
-    for (int i = 0; i < o->C; ++i) { st->xhat[i] = st->enc[i]; st->z[i] = st->enc[i]; }
+    for (int i = 0; i < o->C; ++i) { st->xhat[i] = e[i]; st->z[i] = e[i]; }
   }
   /* Hidden layers: a_k = W_k h_{k-1} + b_k, h_k = max(a_k, 0). */
   const double* hin = st->z;
@@ -464,6 +468,8 @@ static void point_backward(const ora_cfg* c, const ora_layout* o, const double* 
   } else {
     for (int i = 0; i < o->C; ++i) gx[i] = gh[i];
   }
+  if (c->masked)   /* back through the channel mask to the raw encoding */
+    for (int i = 0; i < o->C; ++i) gx[i] *= c->mask[i];
   for (int l = 0; l < o->L; ++l)
     for (int k = 0; k < 8; ++k)
       for (int f = 0; f < o->F; ++f)

@@ -80,7 +80,7 @@ struct Plan {
   KernelSet ks;
   // workspace offsets (bytes)
   int64_t o_params, o_grads, o_m, o_v, o_th, o_part, o_rays, o_wsum, o_enc, o_apred, o_absres, o_loss, o_pix;
-  int64_t o_counts, o_offs, o_recmax, o_recs, o_totals, o_binstart, o_bfb, o_split;
+  int64_t o_counts, o_offs, o_recmax, o_mask, o_recs, o_totals, o_binstart, o_bfb, o_split;
   int n_bins = 0;
   int64_t bytes = 0;
 };
@@ -151,6 +151,7 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
   }
   p.lt.mask = (uint32_t)(T - 1);
   p.lt.L = L;
+  p.lt.on = 0xFFFFFFFFu;
   p.n_tables = c->n_tables > 1 ? c->n_tables : 1;
   p.n_entries = off;
   p.n_table = off * 2 * p.n_tables;
@@ -198,6 +199,7 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
   p.o_counts = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_offs = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_recmax = take(4);
+  p.o_mask = take(32 * 4);
   p.o_recs = take(max_recs * (int64_t)sizeof(BinRec));
   p.o_split = take(2ll * kMaxReduceBlocks * n_sub * (2ll << kBinBits) * 8);
   p.o_sqerr = take(2 * kSqerrBlocks * 8);
@@ -237,6 +239,9 @@ struct nic_model {
   int64_t step = 0;
   int64_t epoch_cached = -1;
   bool grads_dirty = false;   // gradients accumulated by nic_backward and not yet consumed by Adam
+  bool masked = false;        // channel mask set by nic_set_channel_mask
+  float mask[32] = {};        // host copy (source of the device copy)
+  float* mask_dev = nullptr;
   std::vector<int32_t> epoch_order;
   // kernel timing (benchmarks)
   bool timing = false;
@@ -295,6 +300,10 @@ FwdArgs fwd_args(nic_model* m, int mode, int64_t n_points) {
   a.out_act = m->cfg.out_act;
   a.mu_max = (float)m->cfg.mu_max;
   a.ln_eps = (float)m->cfg.ln_eps;
+  a.mask = m->masked ? m->mask_dev : nullptr;
+  if (m->masked)
+    for (int l = 0; l < a.lt.L; ++l)
+      if (m->mask[2 * l] == 0.0f && m->mask[2 * l + 1] == 0.0f) a.lt.on &= ~(1u << l);
   return a;
 }
 
@@ -579,6 +588,7 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   m->offs = (uint32_t*)(ws + p.o_offs);
   m->block_first_bin = (int32_t*)(ws + p.o_bfb);
   m->rec_max = (uint32_t*)(ws + p.o_recmax);
+  m->mask_dev = (float*)(ws + p.o_mask);
   m->recs = (BinRec*)(ws + p.o_recs);
   m->split_acc = (unsigned long long*)(ws + p.o_split);
   m->totals = (uint32_t*)(ws + p.o_totals);
@@ -797,6 +807,60 @@ nic_status nic_field_from_features(nic_model* m, const float* enc_dev, int64_t n
   a.feats = enc_dev;
   a.mu_out = mu_dev;
   NIC_HIP(launch_fwd(m->plan.ks, a, 0, 0, m->stream));
+  return NIC_OK;
+}
+
+nic_status nic_channel_spectrum(nic_model* m, int32_t g_max, float* hf_host) {
+  if (!model_ok(m) || !hf_host) return fail(NIC_EINVAL, "NULL argument");
+  if (g_max < 4 || g_max > 64) return fail(NIC_EINVAL, "g_max must be in [4, 64]");
+  const Plan& pl = m->plan;
+  const int C = pl.C;
+  // scratch inside the record buffer (unused between training steps): points, encodings, 2 fields
+  const int64_t n_max = (int64_t)g_max * g_max * g_max;
+  const int64_t need = n_max * 12 + n_max * C * 4 + 2 * n_max * 16 + 64;
+  if (need > pl.o_split - pl.o_recs) return fail(NIC_EINVAL, "record buffer too small for a %d^3 probe", g_max);
+  char* base = (char*)m->recs;
+  float* xn = (float*)base;
+  float* enc = (float*)(base + n_max * 12);
+  double2* b0 = (double2*)(base + ((n_max * 12 + n_max * C * 4 + 15) & ~(int64_t)15));
+  double2* b1 = b0 + n_max;
+  const int nb = kSqerrBlocks;
+  std::vector<double> h(2 * (size_t)nb);
+  for (int l = 0; l < pl.lt.L; ++l) {
+    const int N = pl.lt.res[l];
+    const int G = std::min(g_max, N);
+    const int v0 = (N - G) / 2;
+    NIC_HIP(launch_probe_points(N, v0, G, xn, m->stream));
+    NIC_HIP(launch_encode(pl.lt, m->params, 0, xn, (int64_t)G * G * G, enc, nullptr, m->stream));
+    for (int f = 0; f < 2; ++f) {
+      NIC_HIP(launch_channel_power(enc, C, 2 * l + f, G, b0, b1, m->sqerr, nb, m->stream));
+      NIC_HIP(hipMemcpyAsync(h.data(), m->sqerr, h.size() * 8, hipMemcpyDeviceToHost, m->stream));
+      NIC_HIP(hipStreamSynchronize(m->stream));
+      double hi = 0.0, tot = 0.0;
+      for (int b = 0; b < nb; ++b) {
+        hi += h[2 * b];
+        tot += h[2 * b + 1];
+      }
+      hf_host[2 * l + f] = tot > 0.0 ? (float)(hi / tot) : 0.0f;
+    }
+  }
+  return NIC_OK;
+}
+
+nic_status nic_set_channel_mask(nic_model* m, const float* mask_host, int32_t n) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (!mask_host) {
+    m->masked = false;
+    return NIC_OK;
+  }
+  if (n != m->plan.C) return fail(NIC_EINVAL, "mask needs %d channels, got %d", m->plan.C, n);
+  for (int c = 0; c < n; ++c) {
+    if (!std::isfinite(mask_host[c])) return fail(NIC_EINVAL, "mask value %d is not finite", c);
+    m->mask[c] = mask_host[c];
+  }
+  NIC_HIP(hipMemcpyAsync(m->mask_dev, m->mask, (size_t)n * 4, hipMemcpyHostToDevice, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  m->masked = true;
   return NIC_OK;
 }
 

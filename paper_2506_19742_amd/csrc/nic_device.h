@@ -210,6 +210,7 @@ struct LevelTab {
   uint32_t mask;                 // T - 1
   int32_t L;
   int32_t bin_shift;             // log2 of the entries per table-gradient bin
+  uint32_t on;                   // bit l: level l is used (a level whose two channels are masked is not)
 };
 
 // Cell g = min(floor(fl32(x * N)), N - 1) and fraction f = x*N - g (exact) along one axis.

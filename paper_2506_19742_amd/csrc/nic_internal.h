@@ -27,6 +27,7 @@ struct FwdArgs {
   int32_t out_act;
   float mu_max;
   float ln_eps;
+  const float* mask;     // [C] channel mask applied before LayerNorm, or NULL (raw encoding stored)
   int32_t dims[3];       // voxel grid (voxels mode)
   const float* xn;       // points mode [n][3]
   const float* feats;    // features mode: encoder outputs [n][2L], channel l * 2 + f
@@ -137,6 +138,9 @@ struct BinReduceArgs {
 hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s);
 size_t bin_reduce_lds();
 const void* bin_reduce_kernel();
+hipError_t launch_probe_points(int N, int v0, int G, float* xn, hipStream_t s);
+hipError_t launch_channel_power(const float* enc, int C, int c, int G, double2* b0, double2* b1, double* partials,
+                                int n_blocks, hipStream_t s);
 hipError_t launch_ssim(const float* gt, const float* pred, int nx, int ny, int nz, double c1, double c2,
                        double* partials, int n_blocks, hipStream_t s);
 hipError_t launch_sqerr(const float* gt, const float* pred, int64_t n, double* partials, int n_blocks,

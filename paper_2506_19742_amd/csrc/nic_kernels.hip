@@ -118,6 +118,11 @@ __device__ __forceinline__ void encode_half(const LevelTab& T, const void* __res
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int lA = 4 * j + q, lB = 4 * j + 2 + q;
+      if (!(((T.on >> lA) | (T.on >> lB)) & 1u)) {   // both levels of the pair unused: skip (wave-uniform)
+        e[4 * j + 2 * q] = 0.0f;
+        e[4 * j + 2 * q + 1] = 0.0f;
+        continue;
+      }
       const int32_t N = h ? T.res[lB] : T.res[lA];
       const uint32_t off = h ? T.off[lB] : T.off[lA];
       const uint32_t st = h ? T.stride[lB] : T.stride[lA];
@@ -161,6 +166,7 @@ __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restri
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int lA = 4 * j + q, lB = 4 * j + 2 + q;
+      if (!(((T.on >> lA) | (T.on >> lB)) & 1u)) continue;   // both levels of the pair unused: no records
       const int32_t N = h ? T.res[lB] : T.res[lA];
       const uint32_t off = h ? T.off[lB] : T.off[lA];
       const uint32_t st = h ? T.stride[lB] : T.stride[lA];
@@ -551,6 +557,10 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_fwd(const FwdArgs a
 #pragma unroll
       for (int r = 0; r < RC; ++r) a.enc_out[(wave_id * RC + r) * kWave + lane] = e[r];
     }
+    if (a.mask) {   // channel mask (Sec. 2.3) between the encoder and LayerNorm
+#pragma unroll
+      for (int r = 0; r < RC; ++r) e[r] *= a.mask[chan(r, h)];
+    }
     float xh[RC], z[RC], rstd;
     ln_forward<C>(e, sp + Ly::s_lng, sp + Ly::s_lnb, a.ln_eps, a.layernorm, h, xh, z, rstd);
 
@@ -624,6 +634,10 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
     float e[RC];
 #pragma unroll
     for (int r = 0; r < RC; ++r) e[r] = wave_valid ? b.enc_in[(wave_id * RC + r) * kWave + lane] : 0.0f;
+    if (a.mask) {   // channel mask (Sec. 2.3) between the encoder and LayerNorm
+#pragma unroll
+      for (int r = 0; r < RC; ++r) e[r] *= a.mask[chan(r, h)];
+    }
     float xh[RC], z[RC], rstd;
     ln_forward<C>(e, sp + Ly::s_lng, sp + Ly::s_lnb, a.ln_eps, a.layernorm, h, xh, z, rstd);
 
@@ -764,6 +778,10 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
       for (int r = 0; r < RC; ++r) gx[r] = gz[r];
     }
 
+    if (a.mask) {   // back through the channel mask to the raw encoding
+#pragma unroll
+      for (int r = 0; r < RC; ++r) gx[r] *= a.mask[chan(r, h)];
+    }
     scatter_half<L>(a.lt, b.recs, cursor, x, h, gx, valid && (rr.hit || vloss), n, tbase, vmax);
   }
   // Largest |record| of the step (positive floats order like their bit patterns): sets the
@@ -1337,6 +1355,97 @@ __global__ void __launch_bounds__(256) k_ssim(const float* __restrict__ gt, cons
     __syncthreads();
   }
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Channel spectra (Sec. 2.3: noisy hash-feature channels are found with an FFT).  For one level of
+// resolution N the probe is the G^3 grid of its own vertices v0 + i (i < G = min(Gmax, N)) around the
+// box centre; each of the level's channels is sampled there, transformed with a 3-D DFT (FP64), and
+// its power split into the high band (max_d |k_d| > G/4, signed frequencies) and the rest (DC
+// excluded).
+// ---------------------------------------------------------------------------------------------
+__global__ void k_probe_points(int N, int v0, int G, float* __restrict__ xn) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)G * G * G) return;
+  const int ix = (int)(q % G), iy = (int)((q / G) % G), iz = (int)(q / ((int64_t)G * G));
+  xn[3 * q] = (float)(v0 + ix) / (float)N;
+  xn[3 * q + 1] = (float)(v0 + iy) / (float)N;
+  xn[3 * q + 2] = (float)(v0 + iz) / (float)N;
+}
+
+// One DFT pass along axis `axis` (0 = x, fastest) of a G^3 complex field [z][y][x]; the first pass
+// reads the real channel c of the encodings enc [G^3][C] instead (in == NULL).
+__global__ void k_dft_axis(const double2* __restrict__ in, const float* __restrict__ enc, int C, int c, int G,
+                           int axis, double2* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)G * G * G) return;
+  const int ix = (int)(q % G), iy = (int)((q / G) % G), iz = (int)(q / ((int64_t)G * G));
+  const int k = axis == 0 ? ix : (axis == 1 ? iy : iz);
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? G : (int64_t)G * G);
+  const int64_t base = q - (int64_t)k * stride;
+  double re = 0.0, im = 0.0;
+  for (int n = 0; n < G; ++n) {
+    const int64_t src = base + (int64_t)n * stride;
+    const double2 v = in ? in[src] : make_double2((double)enc[src * C + c], 0.0);
+    const int j = (int)(((int64_t)k * n) % G);
+    double sn, cs;
+    sincospi(2.0 * (double)j / (double)G, &sn, &cs);
+    re += v.x * cs + v.y * sn;          // v * exp(-2 pi i k n / G)
+    im += v.y * cs - v.x * sn;
+  }
+  out[q] = make_double2(re, im);
+}
+
+// Per-block FP64 sums of the power in the high band (partials[2b]) and of all non-DC power
+// (partials[2b + 1]).
+__global__ void __launch_bounds__(256) k_band_power(const double2* __restrict__ X, int G,
+                                                    double* __restrict__ partials) {
+  __shared__ double sh[256], st[256];
+  double hi = 0.0, tot = 0.0;
+  const int64_t n = (int64_t)G * G * G;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    if (q == 0) continue;
+    const int k[3] = {(int)(q % G), (int)((q / G) % G), (int)(q / ((int64_t)G * G))};
+    int kmax = 0;
+    for (int d = 0; d < 3; ++d) {
+      const int s = k[d] <= G / 2 ? k[d] : G - k[d];
+      kmax = s > kmax ? s : kmax;
+    }
+    const double p = X[q].x * X[q].x + X[q].y * X[q].y;
+    tot += p;
+    if (4 * kmax > G) hi += p;
+  }
+  sh[threadIdx.x] = hi;
+  st[threadIdx.x] = tot;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sh[threadIdx.x] += sh[threadIdx.x + o];
+      st[threadIdx.x] += st[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = sh[0];
+    partials[2 * blockIdx.x + 1] = st[0];
+  }
+}
+
+hipError_t launch_probe_points(int N, int v0, int G, float* xn, hipStream_t s) {
+  const int64_t n = (int64_t)G * G * G;
+  k_probe_points<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(N, v0, G, xn);
+  return hipGetLastError();
+}
+
+hipError_t launch_channel_power(const float* enc, int C, int c, int G, double2* b0, double2* b1, double* partials,
+                                int n_blocks, hipStream_t s) {
+  const int64_t n = (int64_t)G * G * G;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  k_dft_axis<<<g, 256, 0, s>>>(nullptr, enc, C, c, G, 0, b0);
+  k_dft_axis<<<g, 256, 0, s>>>(b0, nullptr, C, c, G, 1, b1);
+  k_dft_axis<<<g, 256, 0, s>>>(b1, nullptr, C, c, G, 2, b0);
+  k_band_power<<<n_blocks, 256, 0, s>>>(b0, G, partials);
+  return hipGetLastError();
 }
 
 // Raw encoding of n points (all levels, natural channel order) and optional corner entries.

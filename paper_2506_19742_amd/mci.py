@@ -8,8 +8,9 @@
    ``pretrain_gt`` follows the paper literally: the ground-truth volume of a single phantom.
 3. ``heldout``: held-out reconstructions whose LN + MLP are imported from a blob (the hash table
    stays freshly initialised), compared with random initialisation.  An arm is
-   ``<fp32|bf16>_<random|mci|mcigt>[_noln]``; ``_noln`` drops the LayerNorm of the encoder (the
-   ablation of the Normalized Hash Encoder; an MCI blob is only loaded into a model of its own form).
+   ``<fp32|bf16>_<random|mci|mcigt>[_noln][_mask]``; ``_noln`` drops the LayerNorm of the encoder (the
+   ablation of the Normalized Hash Encoder; an MCI blob is only loaded into a model of its own form);
+   ``_mask`` masks the channels the FFT measure finds noisy at ``--mask-step`` (Sec. 2.3).
 
 Every compute step runs in libnic's kernels; this module only sequences calls and records timings.
 Command line: ``python -m paper_2506_19742_amd.mci --help``.
@@ -42,8 +43,10 @@ def scan_workload(grid: int, n_ell: int, seed: int, n_views: int, n_det: int, i0
 
 
 def reconstruct(cfg: nic.Config, g, A, gt, n_steps: int, eval_every: int = 100, target_db: float = 30.0,
-                blob: bytes | None = None, stop_at_target: bool = False, log=None):
-    """Trains one model on a scan; returns the PSNR curve, the time/steps to target and the model."""
+                blob: bytes | None = None, stop_at_target: bool = False, log=None, mask_at=None):
+    """Trains one model on a scan; returns the PSNR curve, the time/steps to target and the model.
+    mask_at = (step, threshold): at the first evaluation at or after `step`, channels whose high-band
+    spectral share exceeds `threshold` are masked for the rest of training (Sec. 2.3)."""
     torch = _cuda()
     dev = torch.device("cuda:0")
     m = nic.Model(cfg, g)
@@ -57,6 +60,7 @@ def reconstruct(cfg: nic.Config, g, A, gt, n_steps: int, eval_every: int = 100, 
     t_train = 0.0
     hit = None
     done = 0
+    masked = None
     while done < n_steps:
         k = min(eval_every, n_steps - done)
         torch.cuda.synchronize()
@@ -65,6 +69,16 @@ def reconstruct(cfg: nic.Config, g, A, gt, n_steps: int, eval_every: int = 100, 
         torch.cuda.synchronize()
         t_train += time.perf_counter() - t0
         done += k
+        if mask_at is not None and masked is None and done >= mask_at[0]:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hf = m.channel_spectrum(64)
+            mask = [0.0 if h > mask_at[1] else 1.0 for h in hf]
+            m.set_channel_mask(mask)
+            t_train += time.perf_counter() - t0
+            masked = {"step": done, "hf": [float(h) for h in hf], "mask": mask}
+            if log:
+                log(f"  step {done}: masked channels {[i for i, v in enumerate(mask) if v == 0.0]}")
         vol = m.render_volume(n, n, n)
         p = m.psnr(gtd, vol)
         curve.append((done, t_train, p))
@@ -75,7 +89,7 @@ def reconstruct(cfg: nic.Config, g, A, gt, n_steps: int, eval_every: int = 100, 
             if stop_at_target:
                 break
     final_ssim = m.ssim(gtd, m.render_volume(n, n, n))
-    return {"curve": curve, "hit": hit, "model": m, "proj": proj, "ssim": final_ssim}
+    return {"curve": curve, "hit": hit, "model": m, "proj": proj, "ssim": final_ssim, "masked": masked}
 
 
 def render_table(m, n: int):
@@ -138,6 +152,8 @@ def main(argv=None):
     ap.add_argument("--stage", choices=["calibrate", "pretrain", "pretrain_gt", "heldout", "stability", "views"],
                     required=True)
     ap.add_argument("--views", default="10,20,30,50,100")
+    ap.add_argument("--mask-step", type=int, default=300)
+    ap.add_argument("--mask-threshold", type=float, default=0.8)
     ap.add_argument("--out", default="gpurun_out/mci")
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--depth", type=int, default=4)
@@ -243,14 +259,16 @@ def main(argv=None):
             parts = arm.split("_")
             prec = 1 if parts[0] == "bf16" else 0
             ln = 0 if "noln" in parts[2:] else 1
+            mask_at = (args.mask_step, args.mask_threshold) if "mask" in parts[2:] else None
             use = None if parts[1] == "random" else blobs[parts[1]]
             log(f"held-out {seed} arm {arm}")
             r = reconstruct(cfg_for(prec, 3000 + i, ln), g, A, gt, args.steps, args.eval_every, args.target,
-                            blob=use, log=None)
+                            blob=use, log=log if mask_at else None, mask_at=mask_at)
             r["model"].close()
             best = max(p for _, _, p in r["curve"])
             log(f"  -> hit {r['hit']}, best {best:.2f} dB")
-            results.setdefault(arm, {})[seed] = {"curve": r["curve"], "hit": r["hit"], "ssim": r["ssim"]}
+            results.setdefault(arm, {})[seed] = {"curve": r["curve"], "hit": r["hit"], "ssim": r["ssim"],
+                                                 "masked": r["masked"]}
         json.dump(results, open(f"{args.out}/heldout{args.tag}.json", "w"))
 
 

@@ -60,7 +60,8 @@ EXPORTS = ["nic_describe", "nic_workspace_size", "nic_create", "nic_destroy", "n
            "nic_adam", "nic_zero_grad", "nic_query", "nic_render_volume", "nic_encode",
            "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step",
            "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr",
-           "nic_save_state", "nic_load_state", "nic_field_from_features", "nic_ssim"]
+           "nic_save_state", "nic_load_state", "nic_field_from_features", "nic_ssim",
+           "nic_set_channel_mask", "nic_channel_spectrum"]
 
 _lib = None
 
@@ -107,6 +108,8 @@ def lib():
             "nic_load_state": ([vp, vp, C.c_size_t], C.c_int32),
             "nic_field_from_features": ([vp, vp, C.c_int64, vp], C.c_int32),
             "nic_ssim": ([vp, vp, vp, P(C.c_int32), P(C.c_double)], C.c_int32),
+            "nic_set_channel_mask": ([vp, P(C.c_float), C.c_int32], C.c_int32),
+            "nic_channel_spectrum": ([vp, C.c_int32, P(C.c_float)], C.c_int32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -297,6 +300,20 @@ class Model:
         mu = torch.empty(xn.shape[0], dtype=torch.float32, device=self.ws.device)
         _check(lib().nic_query(self.h, _ptr(xn), xn.shape[0], _ptr(mu)))
         return mu
+
+    def set_channel_mask(self, mask):
+        """Channel mask before LayerNorm (sequence of n_levels * 2 floats), or None to remove it."""
+        if mask is None:
+            _check(lib().nic_set_channel_mask(self.h, None, 0))
+            return
+        arr = (C.c_float * len(mask))(*[float(v) for v in mask])
+        _check(lib().nic_set_channel_mask(self.h, arr, len(mask)))
+
+    def channel_spectrum(self, g_max: int = 64) -> np.ndarray:
+        """High-band power fraction of every encoder channel (see nic_channel_spectrum)."""
+        out = np.zeros(2 * self.cfg.n_levels, np.float32)
+        _check(lib().nic_channel_spectrum(self.h, g_max, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
 
     def field_from_features(self, enc):
         """mu from given encoder outputs [n][2L] (LayerNorm + MLP + output activation only)."""

@@ -124,6 +124,73 @@ def test_query_matches_oracle(ora, tiny, scale):
     assert rel(mu, ora.field(c.oc, p, x)) <= FWD_TOL
 
 
+def test_channel_mask_matches_oracle(ora):
+    """Channel mask before LayerNorm (Sec. 2.3): forward, backward and a training step with some
+    channels off (a pair of levels entirely, so neither is gathered nor scattered) and one scaled, against
+    the oracle with the same mask; then the mask removed.  A model of its own: the step moves it."""
+    import dataclasses
+    c = Case(ora, "tiny64", seed=12)
+    p = random_params(ora, c.oc, 35, 0.05)
+    c.set_params(p)
+    C_ = 2 * c.cfg.n_levels
+    mask = [1.0] * C_
+    # levels 1 and 3 (a pair handled together, channels 2, 3, 6, 7) fully off: skipped
+    mask[1], mask[2], mask[3], mask[6], mask[7], mask[C_ - 1], mask[4] = 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.5
+    oc = dataclasses.replace(c.oc, mask=tuple(mask))
+    c.model.set_channel_mask(mask)
+    try:
+        x = _pts(777, 36)
+        mu = c.model.query(torch.tensor(x, device="cuda")).cpu().numpy()
+        assert rel(mu, ora.field(oc, p, x)) <= FWD_TOL
+        pix, jit, tp, tj = _rays(c, 300, 37)
+        a = c.model.forward(8, tp, tj).cpu().numpy()
+        dA = np.random.default_rng(38).standard_normal(300).astype(np.float32)
+        c.model.zero_grad()
+        c.model.backward(8, tp, tj, torch.tensor(dA, device="cuda"))
+        _, oa, og = ora.ray_batch(oc, c.g, p, float(c.g.angles[8]), c.A[8], pix, jit, dA=dA)
+        assert rel(a, oa) <= FWD_TOL
+        g = c.grads()
+        nt = ora.n_params(oc)[1]
+        assert rel(g[:nt], og[:nt]) <= GRAD_TOL
+        assert rel(g[nt:], og[nt:]) <= GRAD_TOL
+        # a training step with the level skipped (no gathers, no records) against the oracle step
+        c.model.zero_grad()
+        c.model.tensors()[2].zero_()
+        c.model.tensors()[3].zero_()
+        t0 = c.model.get_step()
+        loss = torch.zeros(1, device="cuda")
+        pix2, jit2, tp2, tj2 = _rays(c, 1024, 40)
+        c.model.step(21, tp2, tj2, loss)
+        ol, _, og2 = ora.ray_batch(oc, c.g, p, float(c.g.angles[21]), c.A[21], pix2, jit2)
+        op, om, ov = p.copy(), np.zeros_like(p), np.zeros_like(p)
+        ora.adam(op, og2, om, ov, t0 + 1)
+        assert abs(loss.item() - ol) <= FWD_TOL * abs(ol)
+        assert rel(c.params(), op) <= GRAD_TOL
+        c.set_params(p)
+        with pytest.raises(nic.NicError):
+            c.model.set_channel_mask([1.0] * (C_ - 1))
+    finally:
+        c.model.set_channel_mask(None)
+    mu2 = c.model.query(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert rel(mu2, ora.field(c.oc, p, x)) <= FWD_TOL
+    c.model.close()
+
+
+def test_channel_spectrum_matches_oracle(ora, tiny):
+    """FFT noise measure of every encoder channel (DFT on the GPU in FP64) against numpy's FFT on the
+    oracle's encoding of the same probe points."""
+    c = tiny
+    p = random_params(ora, c.oc, 39, 0.05)
+    c.set_params(p)
+    nt = ora.n_params(c.oc)[1]
+    for g_max in (32, 13):
+        hf = c.model.channel_spectrum(g_max)
+        ohf = ora.channel_hf_fraction(c.oc, p[:nt], g_max)
+        assert np.abs(hf - ohf).max() <= 1e-5, (g_max, hf, ohf)
+    with pytest.raises(nic.NicError):
+        c.model.channel_spectrum(65)
+
+
 def test_field_from_features_matches_oracle(ora, tiny):
     """LayerNorm + MLP + activation on given encoder outputs (the mapping Fig. 3 tracks), fed with the
     GPU's own encoding of 1001 points and with arbitrary feature vectors."""
@@ -386,6 +453,41 @@ def test_paper_scale_sampled_rays(ora):
     assert rel(g[:nt], og[:nt]) <= GRAD_TOL
     assert rel(g[nt:], og[nt:]) <= GRAD_TOL
     c.model.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_largest_workload_sampled_rays(ora, precision):
+    """512^3 workload (T = 2^21, 8192 rays x 320 samples = 2.6 M points per launch, the largest
+    configuration benchmarked): forward over all rays and backward, checked on sampled rays.  FP32 to
+    the parity bars; the precision form to the bounds of its error table."""
+    w = synth.WORKLOADS["ct512"]
+    cfg = nic.config_for(w, precision=precision, seed=3)
+    g = synth.cone_geometry(w.n_det, w.n_views)
+    oc = ocfg(ora, cfg)
+    print(f"[case] ct512 precision {precision} creating model", flush=True)
+    m = nic.Model(cfg, g)
+    p = random_params(ora, oc, 41, 0.05)
+    m.load_params(p)
+    R = cfg.rays_per_step
+    pix, jit = synth.ray_batch(42, g.n_pix, R, cfg.samples_per_ray)
+    tp, tj = torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda")
+    v = 37
+    a = m.forward(v, tp, tj).cpu().numpy()
+    sel = np.random.default_rng(43).choice(R, 16, replace=False)
+    zero_proj = np.zeros(g.n_pix, np.float32)
+    _, oa, _ = ora.ray_batch(oc, g, p, float(g.angles[v]), zero_proj, pix[sel], jit[sel], grad=False)
+    fwd_tol, grad_tol = (FWD_TOL, GRAD_TOL) if precision == 0 else (3e-2, 0.1)
+    assert rel(a[sel], oa) <= fwd_tol
+    dA = np.zeros(R, np.float32)
+    dA[sel] = np.random.default_rng(44).standard_normal(16).astype(np.float32)
+    m.zero_grad()
+    m.backward(v, tp, tj, torch.tensor(dA, device="cuda"))
+    gr = m.flat(m.tensors()[1])
+    _, _, og = ora.ray_batch(oc, g, p, float(g.angles[v]), zero_proj, pix[sel], jit[sel], dA=dA[sel])
+    nt = ora.n_params(oc)[1]
+    assert rel(gr[:nt], og[:nt]) <= grad_tol
+    assert rel(gr[nt:], og[nt:]) <= grad_tol
+    m.close()
 
 
 def test_autograd_function_matches_oracle_and_fd(ora, tiny):

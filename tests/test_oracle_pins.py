@@ -697,3 +697,64 @@ def test_ssim_pins(ora):
     g2[0, 0, 0] = gt.max() + 1.0
     assert ora.ssim(g2, p2) == pytest.approx(ora.ssim(p2, g2), rel=1e-12)
     assert np.isnan(ora.ssim(gt[:10], pred[:10]))
+
+
+@pytest.mark.parametrize("layernorm", [1, 0])
+def test_channel_mask_pins(ora, layernorm):
+    """Channel mask before LayerNorm (Sec. 2.3, masking noisy channels): an all-ones mask changes
+    nothing; masking channel (l, f) is the same field as zeroing feature f of every entry of level l,
+    and the masked channel's table entries receive no gradient."""
+    import dataclasses
+    cfg = ora.Config(**CFG_SMALL, layernorm=layernorm)
+    tot, nt, nd = ora.n_params(cfg)
+    rng = np.random.default_rng(91)
+    params = rng.standard_normal(tot) * 0.5
+    x = rng.random((30, 3)).astype(np.float32)
+    C_ = cfg.n_levels * cfg.feats
+    ones = dataclasses.replace(cfg, mask=tuple([1.0] * C_))
+    assert np.array_equal(ora.field(ones, params, x), ora.field(cfg, params, x))
+    drop = [3, 10]
+    mcfg = dataclasses.replace(cfg, mask=tuple(0.0 if i in drop else 1.0 for i in range(C_)))
+    res, dense, off, size, n = ora.levels(cfg)
+    zeroed = params.copy()
+    for i in drop:
+        l, f = divmod(i, cfg.feats)
+        zeroed[2 * off[l] + f:2 * (off[l] + size[l]):2] = 0.0
+    assert np.allclose(ora.field(mcfg, params, x), ora.field(cfg, zeroed, x), rtol=0, atol=1e-15)
+    dmu = rng.standard_normal(30)
+    g = ora.field_backward(mcfg, params, x, dmu)
+    for i in drop:
+        l, f = divmod(i, cfg.feats)
+        assert np.all(g[2 * off[l] + f:2 * (off[l] + size[l]):2] == 0.0)
+    gz = ora.field_backward(cfg, zeroed, x, dmu)
+    assert np.allclose(g[nt:], gz[nt:], rtol=1e-12, atol=1e-15)
+
+
+def test_channel_spectrum_pins(ora):
+    """FFT noise measure of the encoder channels (Sec. 2.3): a table of independent random entries
+    reads as white noise (high-band share near 1 - 1/8 = 0.875); a dense level holding one cosine
+    period along x over its vertices has all its power at |k| = 1, so its high-band share is 0."""
+    cfg = ora.Config(n_levels=8, log2_table=14, base_res=8, max_res=64, depth=2, width=16)
+    tot, nt, nd = ora.n_params(cfg)
+    rng = np.random.default_rng(95)
+    hf = ora.channel_hf_fraction(cfg, rng.standard_normal(nt), g_max=32)
+    res, dense, off, size, n = ora.levels(cfg)
+    for l in range(cfg.n_levels):
+        if min(32, res[l]) >= 16:
+            assert 0.8 < hf[2 * l] < 0.95 and 0.8 < hf[2 * l + 1] < 0.95, (l, hf[2 * l:2 * l + 2])
+    table = np.zeros(nt)
+    for l in range(cfg.n_levels):
+        if not dense[l]:
+            continue
+        N = int(res[l])
+        v = np.arange((N + 1) ** 3)
+        v0 = v % (N + 1)
+        table[2 * (off[l] + v)] = np.cos(2 * np.pi * v0 / N)
+        table[2 * (off[l] + v) + 1] = np.sin(2 * np.pi * v0 / N)
+    hf = ora.channel_hf_fraction(cfg, table, g_max=32)
+    checked = 0
+    for l in range(cfg.n_levels):
+        if dense[l] and res[l] <= 32:
+            assert hf[2 * l] < 1e-12 and hf[2 * l + 1] < 1e-12, (l, hf[2 * l:2 * l + 2])
+            checked += 1
+    assert checked >= 2
