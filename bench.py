@@ -125,8 +125,8 @@ def main():
         print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build measures "
-              "the single-GPU training step; multi-GPU sharding is design-only.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): it measures the "
+              "training step on one GPU; sharding over several GPUs is a design, not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

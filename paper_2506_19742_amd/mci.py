@@ -154,7 +154,7 @@ def main(argv=None):
     ap.add_argument("--views", default="10,20,30,50,100")
     ap.add_argument("--mask-step", type=int, default=300)
     ap.add_argument("--mask-threshold", type=float, default=0.8)
-    ap.add_argument("--out", default="gpurun_out/mci")
+    ap.add_argument("--out", default="mci_out")
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--depth", type=int, default=4)
     ap.add_argument("--steps", type=int, default=3000)

@@ -1,8 +1,8 @@
 """Precision form: BF16 MFMA operands with FP32 accumulation for the MLP, FP16 copy of the hash table
 for the gathers, FP32 master weights, gradients, LayerNorm statistics, ray sums, loss and Adam.
 
-The error of every result against the FP64 oracle is reported (printed and written to
-gpurun_out/precision_errors.json when that folder exists) and checked against bounds derived from
+The error of every result against the FP64 oracle is reported (printed, and written to
+precision_errors.json in the folder named by NIC_RESULTS_DIR when set) and checked against bounds derived from
 the rounding units: FP16 entries carry 2^-11 relative error, so the encoding stays within ~1e-3 of its
 scale; BF16 operands (2^-8) through a 3-layer MLP put mu and the ray sums within a few 1e-2;
 gradients carry the BF16 error of every operand of the backward MFMAs.
@@ -96,8 +96,8 @@ def test_precision_form_error_table(ora):
     print("precision form, error vs FP64 oracle (max / median, normalised by max |oracle|):")
     for k, (mx, md) in out.items():
         print(f"  {k:16s} {mx:.3e} / {md:.3e}   bound {BOUNDS[k]:.0e}")
-    od = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(od):
+    od = os.environ.get("NIC_RESULTS_DIR", "")
+    if od and os.path.isdir(od):
         with open(os.path.join(od, "precision_errors.json"), "w") as f:
             json.dump({k: {"max": v[0], "median": v[1], "bound": BOUNDS[k]} for k, v in out.items()}, f, indent=1)
     for k, (mx, md) in out.items():
