@@ -705,8 +705,6 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
       float ga[RW];
 #pragma unroll
       for (int R = 0; R < RW; ++R) ga[R] = hb[k][R] > 0.0f ? g[R] : 0.0f;
-      constexpr int dummy = 0;
-      (void)dummy;
       const int Kk = Ly::K(k);
       const float* hin = (k == 0) ? z : hb[k > 0 ? k - 1 : 0];
 #pragma unroll
