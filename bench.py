@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "train pts/s (fwd+bwd); secs to 30 dB PSNR, BF16+MCI vs plain FP32"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {0: 157.3, 1: 2500.0}   # dense FP32 / BF16 matrix cores, MI355X published figures
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 COPY_BYTES = 256 << 20
 
@@ -76,6 +77,17 @@ def algorithmic_bytes(cfg, lay, n_points, fused_adam=False):
         "adam": lay["n_params_padded"] * 32,
         "per_point": payload,
     }
+
+
+def mlp_flops_per_point(cfg):
+    """Multiply-adds x 2 of LayerNorm-free network work per sample point: the forward pass
+    (layer 0: C x W, hidden: (D-1) W x W, head W) and, in the backward kernel, its recomputation
+    plus the data gradients (every layer's transposed product, layer 0 included for LayerNorm) and
+    the weight gradients (one outer product per layer)."""
+    C, W, D = 2 * cfg.n_levels, cfg.mlp_width, cfg.mlp_depth
+    fwd = 2 * (C * W + (D - 1) * W * W + W)
+    bwd = fwd + 2 * (C * W + (D - 1) * W * W + W) + 2 * (C * W + (D - 1) * W * W + W)
+    return fwd, bwd
 
 
 def cpu_baseline(w, g, A, n_rays_sample=1024):
@@ -166,6 +178,19 @@ def main():
     avg_s = kt[dom][0] / kt[dom][1] / 1e3
     achieved = ab[dom] / avg_s / 1e9
     kernel_ms = sum(kt[k][0] for k in kt) / args.steps
+    ffwd, fbwd = mlp_flops_per_point(cfg)
+    kernel_rooflines = {}
+    for k in ("forward", "backward", "bin_reduce", "adam"):
+        if not kt[k][1]:
+            continue
+        t = kt[k][0] / kt[k][1] / 1e3
+        r = {"avg_ms": t * 1e3, "hbm_GBs": ab[k] / t / 1e9, "hbm_frac": ab[k] / t / 1e9 / HBM_PEAK_GBS,
+             "measured_traffic_bytes": measured_traffic(k, w.name, cfg.precision)}
+        if k in ("forward", "backward"):
+            fl = P * (ffwd if k == "forward" else fbwd)
+            r["mfma_TFLOPs"] = fl / t / 1e12
+            r["mfma_frac"] = fl / t / 1e12 / MFMA_PEAK_TFLOPS[cfg.precision]
+        kernel_rooflines[k] = r
 
     out = {
         "metric": METRIC,
@@ -192,6 +217,7 @@ def main():
         "kernel_pts_per_s": P / (kernel_ms / 1e3),
         "kernels": per_kernel,
         "final_loss": float(losses[-1]),
+        "kernel_rooflines": kernel_rooflines,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, w.name, cfg.precision),
