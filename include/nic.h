@@ -270,9 +270,10 @@ int64_t nic_get_step(const nic_model* m);
 
 /* Kernel timing for benchmarks: with enable != 0, every kernel of the training path is bracketed
  * by a pair of HIP events on the model's stream.  nic_kernel_times synchronises the stream and
- * returns, per kernel kind k (0 rays, 1 forward, 2 backward, 3 dense-gradient reduce, 4 adam,
- * 5 bin scan, 6 bin reduce), the total milliseconds ms[k] and the number of launches calls[k]
- * since timing was enabled; ms and calls must hold 8 entries (*count = 7). */
+ * returns, per kernel kind k (0 rays, 1 forward, 2 backward, 3 unused (the dense-gradient reduction
+ * runs inside the bin reduction), 4 adam, 5 bin scan, 6 bin reduce, which includes the dense
+ * reduction), the total milliseconds ms[k] and the number of launches calls[k] since timing was
+ * enabled; ms and calls must hold 8 entries (*count = 7). */
 nic_status nic_set_timing(nic_model* m, int32_t enable);
 nic_status nic_kernel_times(nic_model* m, double* ms, int64_t* calls, int32_t* count);
 

@@ -356,8 +356,9 @@ nic_status adam(nic_model* m) {
 // offsets; the backward pass writes its records there; the bin reduction sums them into the table
 // gradient.  loss_src/loss_n/loss_scale: the per-ray (or per-wave) absolute residuals whose scaled
 // sum is the loss written to loss_dev (when not NULL).  fused: the step's Adam update runs inside
-// the reductions (table in k_bin_reduce / k_bin_combine, LN + MLP in k_reduce) instead of a
-// separate pass over stored gradients; only valid when the gradients start at zero.
+// the reductions (table in k_bin_reduce / k_bin_combine, LN + MLP in the dense blocks of
+// k_bin_combine) instead of a separate pass over stored gradients; only valid when the gradients
+// start at zero.
 nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, int32_t loss_n, float loss_scale,
                    float* loss_dev, bool fused) {
   const Plan& pl = m->plan;
@@ -409,14 +410,23 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
     br.m = m->m;
     br.v = m->v;
     br.th = m->th;
+    DenseReduceArgs& d = br.dense;
+    d.partials = m->partials;
+    d.n_blocks = grid;
+    d.nd_pad = pl.nd_pad;
+    d.nd = (int32_t)pl.n_dense;
+    d.grad_dense = m->grads + pl.dense_off;
+    d.absres = loss_src;
+    d.n_rays = loss_n;
+    d.inv_R = loss_scale;
+    d.loss_out = loss_dev;
+    d.fused = fused ? 1 : 0;
+    d.adam = br.adam;
+    d.p = m->params + pl.dense_off;
+    d.m = m->m + pl.dense_off;
+    d.v = m->v + pl.dense_off;
+    br.dense_blocks = (d.nd + 63) / 64;
     NIC_HIP(launch_bin_reduce(br, m->reduce_grid, m->stream));
-  }
-  {
-    KTimer kt(m, 3);
-    const AdamArgs A = adam_args(m);
-    NIC_HIP(launch_reduce(m->partials, grid, pl.nd_pad, (int)pl.n_dense, m->grads + pl.dense_off, loss_src, loss_n,
-                          loss_scale, loss_dev, fused ? &A : nullptr, m->params + pl.dense_off,
-                          m->m + pl.dense_off, m->v + pl.dense_off, m->stream));
   }
   if (fused) m->step += 1;
   else m->grads_dirty = true;

@@ -307,10 +307,6 @@ template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp_f(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
 }
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
-}
 
 // Sum over the 32 lanes of one half (result in every lane of that half).
 __device__ __forceinline__ float half_sum(float v) {

@@ -100,11 +100,7 @@ hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, i
                       hipStream_t s);
 hipError_t launch_rays(const RaysArgs& a, hipStream_t s);
 hipError_t launch_raysum(const float* wave_sum, int waves_per_ray, int n_rays, float* out, hipStream_t s);
-// Dense gradient and loss; with adam != NULL also Adam on the dense parameters p/m/v (gradient
-// consumed and zeroed).
-hipError_t launch_reduce(const float* partials, int n_blocks, int nd_pad, int nd, float* grad_dense,
-                         const float* absres, int n_rays, float inv_R, float* loss_out, const AdamArgs* adam,
-                         float* p, float* m, float* v, hipStream_t s);
+// Adam over all n parameters from the stored gradient (gradient reset to 0).
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, float ibc1, float ibc2, __half* th, int64_t n_table, int n_cu, hipStream_t s);
 hipError_t launch_fill(float* x, int64_t n, float val, int n_cu, hipStream_t s);
@@ -114,6 +110,21 @@ hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const 
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
                            uint32_t* bin_start, int32_t* block_first_bin, int reduce_grid, uint32_t* rec_max_bits,
                            hipStream_t s);
+// Dense (LayerNorm + MLP) gradient reduction run by the last blocks of k_bin_combine.
+struct DenseReduceArgs {
+  const float* partials;   // [n_blocks][nd_pad] per-block partial sums from k_bwd
+  int32_t n_blocks, nd_pad, nd;
+  float* grad_dense;       // [nd]
+  const float* absres;     // [n_rays] |residual| per ray (or per wave), or NULL
+  int32_t n_rays;
+  float inv_R;
+  float* loss_out;         // loss = sum absres * inv_R, or NULL
+  int32_t fused;           // Adam on p/m/v (gradient left at zero) instead of grad_dense += sum
+  AdamArgs adam;
+  float* p;                // dense parameters and Adam moments [nd]
+  float* m;
+  float* v;
+};
 struct BinReduceArgs {
   const BinRec* recs;             // records grouped by bin
   const uint32_t* bin_start;      // [n_bins + 1] first record of each bin; [n_bins] = total
@@ -134,6 +145,8 @@ struct BinReduceArgs {
   float* m;
   float* v;
   __half* th;
+  DenseReduceArgs dense;
+  int32_t dense_blocks;           // (dense.nd + 63) / 64 extra k_bin_combine blocks
 };
 hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s);
 size_t bin_reduce_lds();

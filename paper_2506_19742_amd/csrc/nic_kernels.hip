@@ -1,6 +1,6 @@
 // Kernels of the training step for gfx950 (one MI355X).
 //
-// Step = k_rays -> k_fwd -> k_bwd -> k_reduce -> k_adam on the model's stream.
+// Step = k_rays -> k_fwd -> bin scan -> k_bwd -> k_bin_reduce -> k_bin_combine on the model's stream.
 //  k_rays   one thread per ray slot: pixel (given or Philox/Feistel draw), FP64 ray setup, A_gt.
 //  k_fwd    four waves per block, 32 points per wave, two lanes per point (lane half h handles
 //           half of the levels): sample position -> hash encode (8 corner gathers per level) ->
@@ -9,11 +9,14 @@
 //  k_bwd    persistent blocks over 128-point chunks: reloads the encoding, recomputes LayerNorm and
 //           the MLP forward, reads the ray's sum -> dA = sign(A - A_gt)/R (Eq. 3) -> MLP backward
 //           on MFMA (data gradients chained in registers, weight gradients via per-wave LDS
-//           transposes), LayerNorm backward, then scatter-adds the corner gradients into the FP32
-//           table gradient.  Dense (LayerNorm + MLP) gradients accumulate in LDS and are written
-//           once per block as partial sums.
-//  k_reduce sums the per-block partials into the dense gradient and the loss.
-//  k_adam   one streaming pass over every parameter: Adam update, gradient reset to 0.
+//           transposes), LayerNorm backward, then writes the corner gradients as records
+//           (entry, w * g) at the block's slots of their gradient bins.  Dense (LayerNorm + MLP)
+//           gradients accumulate in LDS and are written once per block as partial sums.
+//  k_bin_reduce / k_bin_combine sum the table-gradient records bin by bin (exact fixed point) and,
+//           in a training step, run Adam on the table; the last blocks of k_bin_combine sum the
+//           per-block dense partials and run Adam on LayerNorm + MLP, and form the loss.
+//  k_adam   (after a backward pass that left its gradients stored) one streaming pass over every
+//           parameter: Adam update, gradient reset to 0.
 #include "nic_device.h"
 #include "nic_internal.h"
 
@@ -186,27 +189,45 @@ __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restri
       if (__ballot(cont) != 0) {            // wave-uniform: some lane continues a run
         // Segmented inclusive scan over each half-wave on DPP moves: Hillis-Steele steps 1, 2, 4, 8
         // inside each 16-lane row, then lanes 16..31 of the half add lane 15's sum when their run
-        // reaches back into the first row.  start = first lane of this lane's run (max-scan of run
-        // heads, same structure).
-        int start = cont ? 0 : ln;
-        start = max(start, dpp_i<kDppRowShr + 1, 0xF>(start));
-        start = max(start, dpp_i<kDppRowShr + 2, 0xF>(start));
-        start = max(start, dpp_i<kDppRowShr + 4, 0xF>(start));
-        start = max(start, dpp_i<kDppRowShr + 8, 0xF>(start));
-        start = max(start, dpp_i<kDppRowBcast15, 0xA>(start));
+        // reaches back into the first row.  start = first lane of this lane's run (the highest run
+        // head at or below it, from the ballot of heads; lane 0 of a half always is one).  A step
+        // that no lane of the wave takes (every run prefix shorter than its shift) is skipped: this
+        // leaves every sum unchanged.
+        const uint32_t heads = (uint32_t)(__ballot(!cont) >> (32 * h));
+        const int start = 31 - __clz(heads & (0xFFFFFFFFu >> (31 - ln)));
+        const int d = ln - start;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-          float a0, a1;
-          a0 = dpp_f<kDppRowShr + 1, 0xF>(v0[c]); a1 = dpp_f<kDppRowShr + 1, 0xF>(v1[c]);
-          if (ln - 1 >= start) { v0[c] += a0; v1[c] += a1; }
-          a0 = dpp_f<kDppRowShr + 2, 0xF>(v0[c]); a1 = dpp_f<kDppRowShr + 2, 0xF>(v1[c]);
-          if (ln - 2 >= start) { v0[c] += a0; v1[c] += a1; }
-          a0 = dpp_f<kDppRowShr + 4, 0xF>(v0[c]); a1 = dpp_f<kDppRowShr + 4, 0xF>(v1[c]);
-          if (ln - 4 >= start) { v0[c] += a0; v1[c] += a1; }
-          a0 = dpp_f<kDppRowShr + 8, 0xF>(v0[c]); a1 = dpp_f<kDppRowShr + 8, 0xF>(v1[c]);
-          if (ln - 8 >= start) { v0[c] += a0; v1[c] += a1; }
-          a0 = dpp_f<kDppRowBcast15, 0xA>(v0[c]); a1 = dpp_f<kDppRowBcast15, 0xA>(v1[c]);
-          if (ln >= 16 && start <= 15) { v0[c] += a0; v1[c] += a1; }
+          const float a0 = dpp_f<kDppRowShr + 1, 0xF>(v0[c]), a1 = dpp_f<kDppRowShr + 1, 0xF>(v1[c]);
+          if (d >= 1) { v0[c] += a0; v1[c] += a1; }
+        }
+        if (__ballot(d >= 2) != 0) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const float a0 = dpp_f<kDppRowShr + 2, 0xF>(v0[c]), a1 = dpp_f<kDppRowShr + 2, 0xF>(v1[c]);
+            if (d >= 2) { v0[c] += a0; v1[c] += a1; }
+          }
+        }
+        if (__ballot(d >= 4) != 0) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const float a0 = dpp_f<kDppRowShr + 4, 0xF>(v0[c]), a1 = dpp_f<kDppRowShr + 4, 0xF>(v1[c]);
+            if (d >= 4) { v0[c] += a0; v1[c] += a1; }
+          }
+        }
+        if (__ballot(d >= 8) != 0) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const float a0 = dpp_f<kDppRowShr + 8, 0xF>(v0[c]), a1 = dpp_f<kDppRowShr + 8, 0xF>(v1[c]);
+            if (d >= 8) { v0[c] += a0; v1[c] += a1; }
+          }
+        }
+        if (__ballot(ln >= 16 && start <= 15) != 0) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const float a0 = dpp_f<kDppRowBcast15, 0xA>(v0[c]), a1 = dpp_f<kDppRowBcast15, 0xA>(v1[c]);
+            if (ln >= 16 && start <= 15) { v0[c] += a0; v1[c] += a1; }
+          }
         }
       }
       if (active && tail) {
@@ -824,57 +845,53 @@ __global__ void k_raysum(const float* __restrict__ wave_sum, int waves_per_ray, 
   a_pred[r] = A;
 }
 
+// Dense (LayerNorm + MLP) gradient, one 1024-thread block per 64 parameters (block index blk):
 // grad_dense[k] += sum_g partials[g][k] (fixed order: 16 strided groups, then the groups in order);
 // block 0 also forms loss = sum_r absres[r] * inv_R.  With fused != 0 the summed gradient goes into
-// Adam on the dense parameters p/m/v instead and grad_dense is left at zero.
-__global__ void __launch_bounds__(1024) k_reduce(const float* __restrict__ partials, int n_blocks, int nd_pad,
-                                                 int nd, float* __restrict__ grad_dense,
-                                                 const float* __restrict__ absres, int n_rays, float inv_R,
-                                                 float* __restrict__ loss_out, int fused, AdamArgs A,
-                                                 float* __restrict__ pd, float* __restrict__ md,
-                                                 float* __restrict__ vd) {
-  __shared__ float red[1024];
-  const int k = blockIdx.x * 64 + (threadIdx.x & 63);
+// Adam on the dense parameters p/m/v instead and grad_dense is left at zero.  Runs as the last
+// blocks of k_bin_combine (it only needs k_bwd's partials).
+__device__ void dense_reduce_block(const DenseReduceArgs& d, int blk, float* red) {
+  const int k = blk * 64 + (threadIdx.x & 63);
   const int grp = threadIdx.x >> 6;
   float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-  if (k < nd) {
+  if (k < d.nd) {
     int gi = grp;
-    for (; gi + 48 < n_blocks; gi += 64) {
-      s0 += partials[(size_t)gi * nd_pad + k];
-      s1 += partials[(size_t)(gi + 16) * nd_pad + k];
-      s2 += partials[(size_t)(gi + 32) * nd_pad + k];
-      s3 += partials[(size_t)(gi + 48) * nd_pad + k];
+    for (; gi + 48 < d.n_blocks; gi += 64) {
+      s0 += d.partials[(size_t)gi * d.nd_pad + k];
+      s1 += d.partials[(size_t)(gi + 16) * d.nd_pad + k];
+      s2 += d.partials[(size_t)(gi + 32) * d.nd_pad + k];
+      s3 += d.partials[(size_t)(gi + 48) * d.nd_pad + k];
     }
-    for (; gi < n_blocks; gi += 16) s0 += partials[(size_t)gi * nd_pad + k];
+    for (; gi < d.n_blocks; gi += 16) s0 += d.partials[(size_t)gi * d.nd_pad + k];
   }
   red[threadIdx.x] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  if (grp == 0 && k < nd) {
+  if (grp == 0 && k < d.nd) {
     float t = 0.0f;
 #pragma unroll
     for (int q = 0; q < 16; ++q) t += red[threadIdx.x + 64 * q];
-    if (fused) {
-      float pp = pd[k], mm = md[k], vv = vd[k];
-      adam_update(pp, mm, vv, grad_dense[k] + t, A);
-      pd[k] = pp;
-      md[k] = mm;
-      vd[k] = vv;
-      grad_dense[k] = 0.0f;
+    if (d.fused) {
+      float pp = d.p[k], mm = d.m[k], vv = d.v[k];
+      adam_update(pp, mm, vv, d.grad_dense[k] + t, d.adam);
+      d.p[k] = pp;
+      d.m[k] = mm;
+      d.v[k] = vv;
+      d.grad_dense[k] = 0.0f;
     } else {
-      grad_dense[k] += t;
+      d.grad_dense[k] += t;
     }
   }
-  if (blockIdx.x == 0 && loss_out) {
+  if (blk == 0 && d.loss_out) {
     __syncthreads();
     float l = 0.0f;
-    for (int r = threadIdx.x; r < n_rays; r += blockDim.x) l += absres[r];
+    for (int r = threadIdx.x; r < d.n_rays; r += blockDim.x) l += d.absres[r];
     red[threadIdx.x] = l;
     __syncthreads();
     for (int o = 512; o > 0; o >>= 1) {
       if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
       __syncthreads();
     }
-    if (threadIdx.x == 0) *loss_out = red[0] * inv_R;
+    if (threadIdx.x == 0) *d.loss_out = red[0] * d.inv_R;
   }
 }
 
@@ -1206,11 +1223,18 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
 
 // Bins cut by the range boundaries of k_bin_reduce: block j (1 <= j < G') takes the bin holding
 // record T j / G' when that bin starts inside block j - 1's range, adds the int64 slots of blocks
-// j0 = j - 1 .. j1 in order, and adds the result to the FP32 gradient.
+// j0 = j - 1 .. j1 in order, and adds the result to the FP32 gradient.  The grid is the reduction's
+// grid G followed by a.dense_blocks blocks of the dense gradient reduction.
 __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
   constexpr int NB = 1 << kBinBits;
+  __shared__ float red[1024];
+  const int G = gridDim.x - a.dense_blocks;
+  if ((int)blockIdx.x >= G) {   // block-uniform
+    dense_reduce_block(a.dense, blockIdx.x - G, red);
+    return;
+  }
   if (a.fused) {   // bins without records: Adam with a zero gradient (dense Adam semantics)
-    for (int B = blockIdx.x; B < a.n_bins; B += gridDim.x) {
+    for (int B = blockIdx.x; B < a.n_bins; B += G) {
       if (a.bin_start[B] != a.bin_start[B + 1]) continue;
       for (int sub = 0; sub < a.n_sub; ++sub) {
         const uint32_t base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
@@ -1229,7 +1253,7 @@ __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
     }
   }
   const uint64_t T = a.bin_start[a.n_bins];
-  const uint64_t Ge = T < (uint64_t)gridDim.x ? T : (uint64_t)gridDim.x;
+  const uint64_t Ge = T < (uint64_t)G ? T : (uint64_t)G;
   const uint64_t jb = blockIdx.x;
   if (jb == 0 || jb >= Ge) return;
   const uint32_t rs = (uint32_t)(T * jb / Ge), rs_prev = (uint32_t)(T * (jb - 1) / Ge);
@@ -1527,15 +1551,6 @@ hipError_t launch_raysum(const float* ws, int wpr, int n_rays, float* out, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const float* partials, int n_blocks, int nd_pad, int nd, float* grad_dense,
-                         const float* absres, int n_rays, float inv_R, float* loss_out, const AdamArgs* adam,
-                         float* p, float* m, float* v, hipStream_t s) {
-  const AdamArgs A = adam ? *adam : AdamArgs{};
-  k_reduce<<<(nd + 63) / 64, 1024, 0, s>>>(partials, n_blocks, nd_pad, nd, grad_dense, absres, n_rays, inv_R,
-                                          loss_out, adam ? 1 : 0, A, p, m, v);
-  return hipGetLastError();
-}
-
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, float ibc1, float ibc2, __half* th, int64_t n_table, int n_cu, hipStream_t s) {
   const int64_t n4 = n / 4;
@@ -1587,8 +1602,9 @@ size_t bin_reduce_lds() { return (size_t)2 * (1 << kBinBits) * sizeof(unsigned l
 hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s) {
   if (a.bin_shift < kBinBits || a.bin_shift > 31 || a.n_sub != (1 << (a.bin_shift - kBinBits)))
     return hipErrorInvalidValue;
+  if (a.dense_blocks != (a.dense.nd + 63) / 64) return hipErrorInvalidValue;
   k_bin_reduce<<<grid, kReduceThreads, bin_reduce_lds(), s>>>(a);
-  k_bin_combine<<<grid, 1024, 0, s>>>(a);
+  k_bin_combine<<<grid + a.dense_blocks, 1024, 0, s>>>(a);
   return hipGetLastError();
 }
 
