@@ -566,12 +566,14 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   if (e == hipSuccess)
     e = hipFuncSetAttribute(p.ks.bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(p.ks.bwd_lds + bin_lds));
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(bin_reduce_kernel(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bin_reduce_lds());
+    e = hipFuncSetAttribute(bin_reduce_kernel(true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bin_reduce_lds());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(bin_reduce_kernel(false), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bin_reduce_lds());
   int per_cu = 0, per_cu_red = 0;
   if (e == hipSuccess)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.ks.bwd, kBlock, p.ks.bwd_lds + bin_lds);
   if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_red, bin_reduce_kernel(), kReduceThreads, bin_reduce_lds());
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_red, bin_reduce_kernel(true), kReduceThreads, bin_reduce_lds());
   if (e != hipSuccess) {
     delete m;
     return fail(NIC_EHIP, "device query: %s", hipGetErrorString(e));

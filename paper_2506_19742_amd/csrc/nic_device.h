@@ -288,11 +288,14 @@ __device__ __forceinline__ f32x16 mfma32_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
 
 __device__ __forceinline__ float xor32(float v) { return __shfl_xor(v, 32, 64); }
 
-// Adam (Kingma and Ba, Algorithm 1) on one parameter; ibc1, ibc2 = 1 / (1 - beta^t).
+// Adam (Kingma and Ba, Algorithm 1) on one parameter; ibc1, ibc2 = 1 / (1 - beta^t).  No
+// multiply-add contraction: every kernel that runs the update (whichever one a parameter's bin is
+// assigned to) rounds it the same way, so a step does not depend on how the work is partitioned.
 struct AdamArgs {
   float lr, b1, b2, eps, ibc1, ibc2;
 };
 __device__ __forceinline__ void adam_update(float& p, float& m, float& v, float g, const AdamArgs& A) {
+#pragma clang fp contract(off)
   m = A.b1 * m + (1.0f - A.b1) * g;
   v = A.b2 * v + (1.0f - A.b2) * g * g;
   const float mh = m * A.ibc1, vh = v * A.ibc2;

@@ -150,7 +150,7 @@ struct BinReduceArgs {
 };
 hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s);
 size_t bin_reduce_lds();
-const void* bin_reduce_kernel();
+const void* bin_reduce_kernel(bool fused);   // the fused-Adam or the gradient-only form
 hipError_t launch_probe_points(int N, int v0, int G, float* xn, hipStream_t s);
 hipError_t launch_channel_power(const float* enc, int C, int c, int G, double2* b0, double2* b1, double* partials,
                                 int n_blocks, hipStream_t s);

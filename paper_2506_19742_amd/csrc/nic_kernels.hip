@@ -1032,35 +1032,15 @@ __global__ void __launch_bounds__(1024) k_bin_plan(const uint32_t* __restrict__ 
 // its own slot (2j for its first bin, 2j+1 for its last) and k_bin_combine adds the slots in block
 // order after the kernel ends (no cross-block synchronisation inside a kernel).  In a fused step
 // k_bin_combine also runs Adam on the entries of bins without records.
-// Entries of one bin tile, loaded ahead of its flush: parameters and moments (fused Adam) or the
-// gradient.  Nothing is loaded for a bin cut by a range boundary (its tile goes to a slot).
-struct TileAhead {
-  float2 o[kBinTilePer], om[kBinTilePer], ov[kBinTilePer];
-};
-
-__device__ __forceinline__ void tile_prefetch(const BinReduceArgs& a, uint32_t base, int64_t lim, bool split,
-                                              TileAhead& t) {
-  if (split) return;
-#pragma unroll
-  for (int k = 0; k < kBinTilePer; ++k) {
-    const int q = k * kReduceThreads + threadIdx.x;
-    if (q < lim) {
-      if (a.fused) {
-        t.o[k] = reinterpret_cast<const float2*>(a.p)[base + q];
-        t.om[k] = reinterpret_cast<const float2*>(a.m)[base + q];
-        t.ov[k] = reinterpret_cast<const float2*>(a.v)[base + q];
-      } else {
-        t.o[k] = reinterpret_cast<const float2*>(a.grad_table)[base + q];
-      }
-    }
-  }
-}
 
 // Moves the summed tile out (and leaves it zero): Adam on the entries (fused), added to the gradient,
 // or, for a cut bin, stored as int64 in the block's slot.  Called by all threads after a barrier.
+// The entries' parameters and moments (or gradient) are loaded here, not ahead of time: registers
+// held across the record stream would cost the stream its second buffer, and the waves of the
+// block still streaming their next chunk hide the latency.
+template <bool FUSED>
 __device__ __forceinline__ void tile_flush(const BinReduceArgs& a, unsigned long long* tile64, uint32_t base,
-                                           int64_t lim, bool split, size_t slot, int sub, double down,
-                                           TileAhead& t) {
+                                           int64_t lim, bool split, size_t slot, int sub, double down) {
   constexpr int NB = 1 << kBinBits;
   if (split) {
     unsigned long long* S = a.split_acc + (slot * a.n_sub + sub) * (2 * NB);
@@ -1078,17 +1058,21 @@ __device__ __forceinline__ void tile_flush(const BinReduceArgs& a, unsigned long
     tile64[2 * q + 1] = 0ull;
     if (q < lim) {
       const float d0 = (float)((double)s0 * down), d1 = (float)((double)s1 * down);
-      if (a.fused) {
-        adam_update(t.o[k].x, t.om[k].x, t.ov[k].x, d0, a.adam);
-        adam_update(t.o[k].y, t.om[k].y, t.ov[k].y, d1, a.adam);
-        reinterpret_cast<float2*>(a.p)[base + q] = t.o[k];
-        reinterpret_cast<float2*>(a.m)[base + q] = t.om[k];
-        reinterpret_cast<float2*>(a.v)[base + q] = t.ov[k];
-        if (a.th) reinterpret_cast<__half2*>(a.th)[base + q] = __floats2half2_rn(t.o[k].x, t.o[k].y);
+      if constexpr (FUSED) {
+        float2 pp = reinterpret_cast<const float2*>(a.p)[base + q];
+        float2 mm = reinterpret_cast<const float2*>(a.m)[base + q];
+        float2 vv = reinterpret_cast<const float2*>(a.v)[base + q];
+        adam_update(pp.x, mm.x, vv.x, d0, a.adam);
+        adam_update(pp.y, mm.y, vv.y, d1, a.adam);
+        reinterpret_cast<float2*>(a.p)[base + q] = pp;
+        reinterpret_cast<float2*>(a.m)[base + q] = mm;
+        reinterpret_cast<float2*>(a.v)[base + q] = vv;
+        if (a.th) reinterpret_cast<__half2*>(a.th)[base + q] = __floats2half2_rn(pp.x, pp.y);
       } else {
-        t.o[k].x += d0;
-        t.o[k].y += d1;
-        reinterpret_cast<float2*>(a.grad_table)[base + q] = t.o[k];
+        float2 o = reinterpret_cast<const float2*>(a.grad_table)[base + q];
+        o.x += d0;
+        o.y += d1;
+        reinterpret_cast<float2*>(a.grad_table)[base + q] = o;
       }
     }
   }
@@ -1102,6 +1086,7 @@ __device__ __forceinline__ void rec_add(unsigned long long* tile64, const BinRec
   }
 }
 
+template <bool FUSED>
 __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceArgs a) {
   extern __shared__ unsigned long long tile64[];
   __shared__ uint32_t sb[65];                                      // bin starts of the block's first bins
@@ -1128,7 +1113,6 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
   int64_t lim;
   bool split;
   double up, down;
-  TileAhead ta;
   auto begin_segment = [&](int sub) {
     seg_end = min(re, b_end);
     split = b_start < rs || b_end > re;
@@ -1139,28 +1123,20 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
     down = ldexp(1.0, -e);
     base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
     lim = min((int64_t)NB, a.n_entries - (int64_t)base);
-    tile_prefetch(a, base, lim, split, ta);
   };
 
   if (a.n_sub == 1) {
     // One continuous stream over [rs, re) in chunks of CH records, the next chunk's loads in flight
-    // while the current one is added; a segment ends (barrier, flush, barrier) wherever its bin ends.
-    begin_segment(0);
-    BinRec cur[U], nxt[U];
+    // while the current one is added (two record buffers taking turns, so no register copies wait
+    // for loads); a segment ends (barrier, flush, barrier) wherever its bin ends.  Record loads are
+    // unpredicated (positions past re re-read record re - 1, which is never added) so that the wait
+    // for the current chunk leaves the next chunk's loads outstanding.
+    auto load = [&](BinRec (&buf)[U], uint32_t cb) {
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const uint32_t r = rs + k * kReduceThreads + threadIdx.x;
-      if (r < re) cur[k] = a.recs[r];
-    }
-    for (uint32_t cb = rs; cb < re; cb += CH) {
+      for (int k = 0; k < U; ++k) buf[k] = a.recs[min(cb + k * kReduceThreads + threadIdx.x, re - 1)];
+    };
+    auto add_chunk = [&](const BinRec (&cur)[U], uint32_t cb) {
       const uint32_t ce = min(re, cb + CH);
-      if (ce < re) {
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-          const uint32_t r = ce + k * kReduceThreads + threadIdx.x;
-          if (r < re) nxt[k] = a.recs[r];
-        }
-      }
       uint32_t lo = cb;
       for (;;) {
         const uint32_t hi = min(seg_end, ce);
@@ -1169,11 +1145,11 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
           const uint32_t r = cb + k * kReduceThreads + threadIdx.x;
           if (r >= lo && r < hi) rec_add(tile64, cur[k], base, up);
         }
-        if (seg_end > ce) break;                                   // the segment goes on in the next chunk
+        if (seg_end > ce) return;                                  // the segment goes on in the next chunk
         __syncthreads();
-        tile_flush(a, tile64, base, lim, split, 2 * (size_t)jb + (B == first_bin ? 0 : 1), 0, down, ta);
+        tile_flush<FUSED>(a, tile64, base, lim, split, 2 * (size_t)jb + (B == first_bin ? 0 : 1), 0, down);
         __syncthreads();
-        if (seg_end >= re) break;                                  // the block's range is done
+        if (seg_end >= re) return;                                 // the block's range is done
         lo = seg_end;
         do {                                                       // next bin with records
           ++B;
@@ -1181,10 +1157,18 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
           b_end = bstart(B + 1);
         } while (b_end <= b_start);
         begin_segment(0);
-        if (lo >= ce) break;
+        if (lo >= ce) return;
       }
-#pragma unroll
-      for (int k = 0; k < U; ++k) cur[k] = nxt[k];
+    };
+    begin_segment(0);
+    BinRec buf0[U], buf1[U];
+    load(buf0, rs);
+    for (uint32_t cb = rs; cb < re; cb += 2 * CH) {
+      load(buf1, cb + CH);
+      add_chunk(buf0, cb);
+      if (cb + CH >= re) break;
+      load(buf0, cb + 2 * CH);
+      add_chunk(buf1, cb + CH);
     }
     return;
   }
@@ -1208,7 +1192,7 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
           if (r0 + k * kReduceThreads + (int)threadIdx.x < cnt) rec_add(tile64, rc[k], base, up);
       }
       __syncthreads();
-      tile_flush(a, tile64, base, lim, split, 2 * (size_t)jb + (B == first_bin ? 0 : 1), sub, down, ta);
+      tile_flush<FUSED>(a, tile64, base, lim, split, 2 * (size_t)jb + (B == first_bin ? 0 : 1), sub, down);
       __syncthreads();
     }
     pos = seg_end;
@@ -1603,12 +1587,15 @@ hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s) {
   if (a.bin_shift < kBinBits || a.bin_shift > 31 || a.n_sub != (1 << (a.bin_shift - kBinBits)))
     return hipErrorInvalidValue;
   if (a.dense_blocks != (a.dense.nd + 63) / 64) return hipErrorInvalidValue;
-  k_bin_reduce<<<grid, kReduceThreads, bin_reduce_lds(), s>>>(a);
+  if (a.fused) k_bin_reduce<true><<<grid, kReduceThreads, bin_reduce_lds(), s>>>(a);
+  else k_bin_reduce<false><<<grid, kReduceThreads, bin_reduce_lds(), s>>>(a);
   k_bin_combine<<<grid + a.dense_blocks, 1024, 0, s>>>(a);
   return hipGetLastError();
 }
 
-const void* bin_reduce_kernel() { return reinterpret_cast<const void*>(&k_bin_reduce); }
+const void* bin_reduce_kernel(bool fused) {
+  return fused ? reinterpret_cast<const void*>(&k_bin_reduce<true>) : reinterpret_cast<const void*>(&k_bin_reduce<false>);
+}
 
 hipError_t launch_ssim(const float* gt, const float* pred, int nx, int ny, int nz, double c1, double c2,
                        double* partials, int n_blocks, hipStream_t s) {

@@ -349,6 +349,44 @@ def test_step_consumes_pending_gradient(ora, tiny):
     assert float(c.model.tensors()[1].abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_step_equals_backward_then_adam(ora, precision):
+    """A training step runs Adam inside its reductions: in the bin reduction for bins one block
+    holds, in the combine kernel for bins cut between blocks and for bins without records, and in
+    the dense blocks for LayerNorm + MLP.  The same step as a stored-gradient backward pass (dA =
+    sign(A - A_gt) / R, Eq. 3) followed by the one separate Adam pass gives the same parameters,
+    moments and FP16 table bit for bit: the update does not depend on which kernel runs it."""
+    w = synth.WORKLOADS["tiny64"]
+    ph, g, A = synth.scan(w)
+    proj = torch.tensor(A, device="cuda")
+    models = []
+    for _ in range(2):
+        m = nic.Model(nic.config_for(w, seed=41, precision=precision), g)
+        m.set_projections(proj)
+        m.train(2, want_loss=False)            # moments away from zero
+        models.append(m)
+    a, b = models
+    for k in range(4):
+        assert torch.equal(a.tensors()[k], b.tensors()[k])
+    R, v = w.rays, 29
+    pix, jit = synth.ray_batch(45, g.n_pix, R, w.samples)
+    tp, tj = torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda")
+    a.step(v, tp, tj)
+    Ab = b.forward(v, tp, tj).cpu().numpy()
+    res = Ab - A[v].reshape(-1)[pix]
+    dA = np.sign(res).astype(np.float32) * (np.float32(1.0) / np.float32(R))
+    b.backward(v, tp, tj, torch.tensor(dA, device="cuda"))
+    b.adam()
+    assert a.get_step() == b.get_step()
+    ta, tb = a.tensors(), b.tensors()
+    for k in (0, 1, 2, 3):                         # params, gradient (zero in both), moments
+        assert torch.equal(ta[k], tb[k]), k
+    if precision:
+        assert torch.equal(ta[4], tb[4])
+    for m in models:
+        m.close()
+
+
 def test_device_draws_match_oracle(ora, tiny):
     """Pixels (Feistel over Philox, cycle walking) and jitter drawn on the GPU, bit for bit."""
     c = tiny
