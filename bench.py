@@ -126,7 +126,15 @@ def main():
                     help="also time forward-only inference of the full n^3 volume (voxel centres)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB (counter calibration) and exit")
+    ap.add_argument("--ubench", action="store_true",
+                    help="only run the memory-ceiling microbenchmark (nic_ubench, built by build()) and exit")
     args = ap.parse_args()
+    if args.ubench:
+        import subprocess
+        exe = os.path.join(ROOT, "paper_2506_19742_amd", "nic_ubench")
+        if not os.path.exists(exe):
+            sys.exit(f"{exe} is missing: run __graft_entry__.build() first")
+        sys.exit(subprocess.run([exe]).returncode)
     if args.copy_calibration:
         import torch
         x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")

@@ -1,7 +1,8 @@
-"""Builds libnic.so (HIP for gfx950) in-tree with hipcc.
+"""Builds libnic.so (HIP for gfx950) in-tree with hipcc, and the memory-ceiling microbenchmark.
 
 Every HIP source is compiled for gfx950 only, with packed-FP32 instructions disabled and hardware
-FP32 atomics; the objects are linked into paper_2506_19742_amd/libnic.so next to this file.
+FP32 atomics; the objects are linked into paper_2506_19742_amd/libnic.so next to this file.  The
+microbenchmark (csrc/ubench.hip, a program of its own) becomes paper_2506_19742_amd/nic_ubench.
 """
 from __future__ import annotations
 
@@ -15,6 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnic.so")
+UBENCH = os.path.join(HERE, "nic_ubench")
 BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -41,17 +43,31 @@ def _compile(src: str, extra) -> str:
     return obj
 
 
+def _build_ubench() -> str:
+    tmp = UBENCH + ".tmp"
+    cmd = [HIPCC, *FLAGS, os.path.join(CSRC, "ubench.hip"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+        raise RuntimeError(f"hipcc failed for ubench.hip:\n{msg}")
+    os.replace(tmp, UBENCH)
+    return UBENCH
+
+
 def build(verbose: bool = False, extra=()) -> str:
-    """Compiles every source for gfx950 and links libnic.so; returns its path."""
+    """Compiles every source for gfx950, links libnic.so and builds nic_ubench; returns the
+    library's path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES) + 1)) as ex:
+        ub = ex.submit(_build_ubench)
         objs = list(ex.map(lambda s: _compile(s, list(extra)), SOURCES))
+        ub.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", UBENCH)
     return LIB
 
 
