@@ -33,13 +33,14 @@ COPY_BYTES = 256 << 20
 
 
 def kernel_source_sha() -> str:
-    """Hash of the HIP sources: measured traffic is used only for the kernels it was taken on."""
+    """Hash of the HIP sources of libnic (its .hip files and the headers): measured traffic is used
+    only for the kernels it was taken on."""
     import hashlib
+    from paper_2506_19742_amd import build as _build
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2506_19742_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in sorted(os.listdir(_build.CSRC)):
+        if f.endswith(".h") or f in _build.SOURCES:
+            h.update(open(os.path.join(_build.CSRC, f), "rb").read())
     return h.hexdigest()[:16]
 
 
