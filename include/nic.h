@@ -167,12 +167,14 @@ int32_t nic_view_for_step(const nic_model* m, int64_t step);
 nic_status nic_draw_rays(nic_model* m, int64_t step, int32_t* pix_dev, float* jitter_dev);
 
 /* Forward pass only (Eq. 1): a_pred_dev (device float32 [n_rays]) = ray sums of n_rays rays of
- * `view` with the given pixels and jitter (both required). n_rays <= rays_per_step. */
+ * `view` with the given pixels and jitter (both required). 0 <= n_rays <= rays_per_step, else
+ * NIC_EINVAL; n_rays == 0 does nothing (the pointers are not used). */
 nic_status nic_forward(nic_model* m, int32_t view, const int32_t* pix_dev, const float* jitter_dev,
                        int32_t n_rays, float* a_pred_dev);
 
 /* Backward pass for an upstream gradient dA_dev (device float32 [n_rays], d loss / d A_pred) of
- * the same rays: accumulates parameter gradients into the grads tensor (not zeroed first). */
+ * the same rays: accumulates parameter gradients into the grads tensor (not zeroed first).
+ * Same n_rays rules as nic_forward. */
 nic_status nic_backward(nic_model* m, int32_t view, const int32_t* pix_dev, const float* jitter_dev,
                         int32_t n_rays, const float* dA_dev);
 
@@ -184,7 +186,7 @@ nic_status nic_adam(nic_model* m);
 nic_status nic_zero_grad(nic_model* m);
 
 /* mu at n points given in normalised coordinates (device float32 [n][3] in [0, 1]) into mu_dev
- * (device float32 [n]). */
+ * (device float32 [n]).  n == 0 does nothing; n < 0 is NIC_EINVAL. */
 nic_status nic_query(nic_model* m, const float* xn_dev, int64_t n, float* mu_dev);
 
 /* Channel mask (Sec. 2.3: channels of the hash features that carry only noise, found with an FFT,

@@ -760,9 +760,9 @@ nic_status nic_forward(nic_model* m, int32_t view, const int32_t* pix_dev, const
                        float* a_pred_dev) {
   if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
   if (view < 0 || view >= m->n_views) return fail(NIC_EINVAL, "view %d out of range", view);
-  if (!pix_dev || !jitter_dev || !a_pred_dev) return fail(NIC_EINVAL, "NULL argument");
   if (n_rays < 0 || n_rays > m->cfg.rays_per_step) return fail(NIC_EINVAL, "n_rays out of range");
   if (n_rays == 0) return NIC_OK;
+  if (!pix_dev || !jitter_dev || !a_pred_dev) return fail(NIC_EINVAL, "NULL argument");
   nic_status st = rays(m, view, pix_dev, n_rays, (uint32_t)m->step, nullptr, nullptr);
   if (st) return st;
   const int64_t P = (int64_t)n_rays * m->cfg.samples_per_ray;
@@ -778,9 +778,9 @@ nic_status nic_backward(nic_model* m, int32_t view, const int32_t* pix_dev, cons
                         const float* dA_dev) {
   if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
   if (view < 0 || view >= m->n_views) return fail(NIC_EINVAL, "view %d out of range", view);
-  if (!pix_dev || !jitter_dev || !dA_dev) return fail(NIC_EINVAL, "NULL argument");
   if (n_rays < 0 || n_rays > m->cfg.rays_per_step) return fail(NIC_EINVAL, "n_rays out of range");
   if (n_rays == 0) return NIC_OK;
+  if (!pix_dev || !jitter_dev || !dA_dev) return fail(NIC_EINVAL, "NULL argument");
   nic_status st = rays(m, view, pix_dev, n_rays, (uint32_t)m->step, nullptr, nullptr);
   if (st) return st;
   return ray_fwd_bwd(m, n_rays, jitter_dev, dA_dev, nullptr, false);

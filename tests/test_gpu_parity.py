@@ -387,6 +387,40 @@ def test_fused_step_equals_backward_then_adam(ora, precision):
         m.close()
 
 
+def test_empty_and_out_of_range_inputs(ora, tiny):
+    """Empty batches are no-ops (the null pointers of empty tensors are never used); more rays than a
+    step holds, a view outside the scan and a negative point count are refused, and nothing moves."""
+    c = tiny
+    p = random_params(ora, c.oc, 47, 0.05)
+    c.set_params(p)
+    c.model.zero_grad()
+    p0 = c.model.tensors()[0].clone()
+    N = c.cfg.samples_per_ray
+    e_i = torch.empty(0, dtype=torch.int32, device="cuda")
+    e_f = torch.empty((0, N), dtype=torch.float32, device="cuda")
+    assert c.model.forward(3, e_i, e_f).numel() == 0
+    c.model.backward(3, e_i, e_f, torch.empty(0, device="cuda"))
+    assert c.model.query(torch.empty((0, 3), device="cuda")).numel() == 0
+    R = c.cfg.rays_per_step
+    pix, jit = synth.ray_batch(48, c.g.n_pix, R + 1, N)
+    tp, tj = torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda")
+    with pytest.raises(nic.NicError):
+        c.model.forward(3, tp, tj)
+    with pytest.raises(nic.NicError):
+        c.model.backward(3, tp, tj, torch.zeros(R + 1, device="cuda"))
+    with pytest.raises(nic.NicError):
+        c.model.forward(len(c.g.angles), tp[:R], tj[:R])
+    with pytest.raises(nic.NicError):
+        nic._check(nic.lib().nic_query(c.model.h, None, -1, None))
+    torch.cuda.synchronize()
+    assert torch.equal(c.model.tensors()[0], p0)
+    assert float(c.model.tensors()[1].abs().max()) == 0.0
+    # the largest batch a step holds is accepted and matches the oracle
+    a = c.model.forward(5, tp[:R], tj[:R]).cpu().numpy()
+    _, oa, _ = ora.ray_batch(c.oc, c.g, p, float(c.g.angles[5]), c.A[5], pix[:R], jit[:R], grad=False)
+    assert rel(a, oa) <= FWD_TOL
+
+
 def test_device_draws_match_oracle(ora, tiny):
     """Pixels (Feistel over Philox, cycle walking) and jitter drawn on the GPU, bit for bit."""
     c = tiny
