@@ -80,7 +80,7 @@ struct Plan {
   KernelSet ks;
   // workspace offsets (bytes)
   int64_t o_params, o_grads, o_m, o_v, o_th, o_part, o_rays, o_wsum, o_enc, o_apred, o_absres, o_loss, o_pix;
-  int64_t o_counts, o_offs, o_recmax, o_mask, o_recs, o_totals, o_binstart, o_bfb, o_split;
+  int64_t o_counts, o_offs, o_recmax, o_mask, o_recs, o_totals, o_binstart, o_bfb, o_bstart, o_split;
   int n_bins = 0;
   int64_t bytes = 0;
 };
@@ -196,6 +196,7 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
   p.o_totals = take((int64_t)p.n_bins * 4);
   p.o_binstart = take((int64_t)(p.n_bins + 1) * 4);
   p.o_bfb = take((int64_t)kMaxReduceBlocks * 4);
+  p.o_bstart = take((int64_t)(kMaxReduceBlocks + 1) * 4);
   p.o_counts = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_offs = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_recmax = take(4);
@@ -228,6 +229,7 @@ struct nic_model {
   int32_t* pix = nullptr;
   uint32_t *counts = nullptr, *offs = nullptr, *totals = nullptr, *bin_start = nullptr;
   int32_t* block_first_bin = nullptr;
+  uint32_t* block_start = nullptr;   // [reduce grid + 1] record ranges of the bin reduction
   uint32_t* rec_max = nullptr;
   BinRec* recs = nullptr;
   unsigned long long* split_acc = nullptr;
@@ -376,8 +378,8 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   }
   {
     KTimer kt(m, 5);
-    NIC_HIP(launch_bin_scan(m->counts, pl.n_bins, grid, m->offs, m->totals, m->bin_start, m->block_first_bin,
-                            m->reduce_grid, m->rec_max, m->stream));
+    NIC_HIP(launch_bin_scan(m->counts, pl.n_bins, grid, m->offs, m->totals, m->bin_start, m->block_start,
+                            m->block_first_bin, m->reduce_grid, m->rec_max, m->stream));
   }
   b.enc_in = m->enc;
   b.a_pred_out = m->apred;
@@ -397,6 +399,7 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
     br.recs = m->recs;
     br.bin_start = m->bin_start;
     br.block_first_bin = m->block_first_bin;
+    br.block_start = m->block_start;
     br.n_bins = pl.n_bins;
     br.rec_max_bits = m->rec_max;
     br.grad_table = m->grads;
@@ -599,6 +602,7 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   m->counts = (uint32_t*)(ws + p.o_counts);
   m->offs = (uint32_t*)(ws + p.o_offs);
   m->block_first_bin = (int32_t*)(ws + p.o_bfb);
+  m->block_start = (uint32_t*)(ws + p.o_bstart);
   m->rec_max = (uint32_t*)(ws + p.o_recmax);
   m->mask_dev = (float*)(ws + p.o_mask);
   m->recs = (BinRec*)(ws + p.o_recs);

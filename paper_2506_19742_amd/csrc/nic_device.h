@@ -22,6 +22,7 @@ constexpr int kBinBits = 12;         // reduction tile: 2^12 entries (64 KB of i
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kReduceThreads = 1024;  // threads of a bin-reduction block
 constexpr int kBinTilePer = (1 << kBinBits) / kReduceThreads;  // tile entries per thread
+constexpr unsigned kFlushCost = 16384;  // a tile flush costs about as much time as streaming this many records
 
 // One corner contribution to the table gradient: entry and the two feature gradients.
 struct BinRec {

@@ -107,9 +107,10 @@ hipError_t launch_fill(float* x, int64_t n, float val, int n_cu, hipStream_t s);
 hipError_t launch_to_half(const float* src, __half* dst, int64_t n, int n_cu, hipStream_t s);
 hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const InitArgs& ia, int n_cu,
                        hipStream_t s);
+// bin_start: [n_bins + 1]; block_start: [reduce_grid + 1] record ranges of the bin reduction's blocks.
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
-                           uint32_t* bin_start, int32_t* block_first_bin, int reduce_grid, uint32_t* rec_max_bits,
-                           hipStream_t s);
+                           uint32_t* bin_start, uint32_t* block_start, int32_t* block_first_bin, int reduce_grid,
+                           uint32_t* rec_max_bits, hipStream_t s);
 // Dense (LayerNorm + MLP) gradient reduction run by the last blocks of k_bin_combine.
 struct DenseReduceArgs {
   const float* partials;   // [n_blocks][nd_pad] per-block partial sums from k_bwd
@@ -128,6 +129,7 @@ struct DenseReduceArgs {
 struct BinReduceArgs {
   const BinRec* recs;             // records grouped by bin
   const uint32_t* bin_start;      // [n_bins + 1] first record of each bin; [n_bins] = total
+  const uint32_t* block_start;     // [G' + 1] first record of each block's range, G' = min(grid, records)
   const int32_t* block_first_bin; // [grid] bin holding the first record of each block's range
   int32_t n_bins;
   int32_t bin_shift;              // log2 entries per bin

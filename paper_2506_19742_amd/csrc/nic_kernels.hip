@@ -983,43 +983,73 @@ __global__ void __launch_bounds__(256) k_bin_rowscan(const uint32_t* __restrict_
 }
 
 // Record offsets, step 2 (one block): bin starts (exclusive scan of the bin totals, with the total T
-// at index n_bins) and, for the bin reduction, the first bin of each block's record range.  The
-// reduction splits [0, T) evenly over G' = min(G, T) blocks: block j takes [T j / G', T (j+1) / G').
+// at index n_bins), and the ranges of the bin reduction's G' = min(G, T) blocks.  A block's time is its
+// records plus a flush for every bin it ends, so the ranges split the cost (records + kFlushCost per
+// non-empty bin, the flush counted at the bin's end) evenly: block j starts at the record where the
+// cost reaches C j / G' (a boundary inside a bin's flush share falls on the bin's end).  Ranges may be
+// empty.  block_first_bin[j]: the bin holding record block_start[j] (any bin when that is T).
 __global__ void __launch_bounds__(1024) k_bin_plan(const uint32_t* __restrict__ totals, int n_bins, int G,
                                                    uint32_t* __restrict__ bin_start,
+                                                   uint32_t* __restrict__ block_start,
                                                    int32_t* __restrict__ block_first_bin,
                                                    uint32_t* __restrict__ rec_max_bits) {
   if (threadIdx.x == 0) *rec_max_bits = 0u;
   __shared__ uint32_t part[1024];
+  __shared__ unsigned long long cpart[1024];
   const int t = threadIdx.x, nt = blockDim.x;
   const int per = (n_bins + nt - 1) / nt;
   const int b0 = t * per, b1 = min(n_bins, b0 + per);
   uint32_t srec = 0;
-  for (int b = b0; b < b1; ++b) srec += totals[b];
+  unsigned long long scost = 0;
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t tot = totals[b];
+    srec += tot;
+    scost += tot ? (unsigned long long)tot + kFlushCost : 0ull;
+  }
   part[t] = srec;
+  cpart[t] = scost;
   __syncthreads();
   for (int o = 1; o < nt; o <<= 1) {
     const uint32_t ar = t >= o ? part[t - o] : 0u;
+    const unsigned long long ac = t >= o ? cpart[t - o] : 0ull;
     __syncthreads();
     part[t] += ar;
+    cpart[t] += ac;
     __syncthreads();
   }
-  const uint64_t T = part[nt - 1];
+  const uint64_t T = part[nt - 1], C = cpart[nt - 1];
   const uint64_t Ge = T < (uint64_t)G ? T : (uint64_t)G;
   uint32_t rec = part[t] - srec;
+  unsigned long long cst = cpart[t] - scost;
   for (int b = b0; b < b1; ++b) {
     const uint32_t tot = totals[b];
     bin_start[b] = rec;
-    if (tot > 0) {   // blocks j whose range starts inside [rec, rec + tot): ceil(rec G'/T) <= j < ceil((rec+tot) G'/T)
-      const uint64_t j0 = ((uint64_t)rec * Ge + T - 1) / T, j1 = ((uint64_t)(rec + tot) * Ge + T - 1) / T;
-      for (uint64_t jj = j0; jj < j1; ++jj) block_first_bin[jj] = b;
+    if (tot > 0) {   // blocks j whose cost boundary C j / G' lies in [cst, cst + tot + F)
+      const unsigned long long c1 = cst + tot + kFlushCost;
+      const uint64_t j0 = (cst * Ge + C - 1) / C, j1 = min((c1 * Ge + C - 1) / C, Ge);
+      for (uint64_t j = j0; j < j1; ++j) {
+        const uint64_t tj = C * j / Ge - cst;
+        if (tj < tot) {
+          block_start[j] = rec + (uint32_t)tj;
+          block_first_bin[j] = b;
+        } else {   // at the bin's end: the block starts in the next bin with records (or at T, empty)
+          block_start[j] = rec + tot;
+          int nb = b + 1;
+          while (nb < n_bins && totals[nb] == 0) ++nb;
+          block_first_bin[j] = nb < n_bins ? nb : n_bins - 1;
+        }
+      }
+      cst = c1;
     }
     rec += tot;
   }
-  if (t == nt - 1) bin_start[n_bins] = (uint32_t)T;
+  if (t == nt - 1) {
+    bin_start[n_bins] = (uint32_t)T;
+    block_start[Ge] = (uint32_t)T;
+  }
 }
 
-// Table gradient from the records.  Block j streams its even share of the records (grouped by bin)
+// Table gradient from the records.  Block j streams its share of the records (grouped by bin)
 // and sums each bin's part in a 2^kBinBits-entry LDS tile (one pass over the part per tile when a
 // bin spans several tiles).  The tile accumulates in int64 fixed point: LDS integer atomics are an
 // order of magnitude faster than LDS float atomics on gfx950, and integer sums are exact, so the
@@ -1096,7 +1126,8 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
   const uint64_t Ge = T < (uint64_t)gridDim.x ? T : (uint64_t)gridDim.x;
   const uint64_t jb = blockIdx.x;
   if (jb >= Ge) return;                                            // block-uniform
-  const uint32_t rs = (uint32_t)(T * jb / Ge), re = (uint32_t)(T * (jb + 1) / Ge);
+  const uint32_t rs = a.block_start[jb], re = a.block_start[jb + 1];
+  if (rs >= re) return;                                            // an empty range
   const float vmax = __uint_as_float(*a.rec_max_bits);
   int ev;
   frexpf(vmax, &ev);                                               // vmax < 2^ev
@@ -1206,8 +1237,8 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
 }
 
 // Bins cut by the range boundaries of k_bin_reduce: block j (1 <= j < G') takes the bin holding
-// record T j / G' when that bin starts inside block j - 1's range, adds the int64 slots of blocks
-// j0 = j - 1 .. j1 in order, and adds the result to the FP32 gradient.  The grid is the reduction's
+// record block_start[j] when that bin starts inside block j - 1's range, adds the int64 slots of the
+// blocks j0 = j - 1 .. j1 that hold part of it in order, and adds the result to the FP32 gradient.  The grid is the reduction's
 // grid G followed by a.dense_blocks blocks of the dense gradient reduction.
 __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
   constexpr int NB = 1 << kBinBits;
@@ -1240,12 +1271,14 @@ __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
   const uint64_t Ge = T < (uint64_t)G ? T : (uint64_t)G;
   const uint64_t jb = blockIdx.x;
   if (jb == 0 || jb >= Ge) return;
-  const uint32_t rs = (uint32_t)(T * jb / Ge), rs_prev = (uint32_t)(T * (jb - 1) / Ge);
+  const uint32_t rs = a.block_start[jb], rs_prev = a.block_start[jb - 1];
+  if (rs >= T) return;
   const int B = a.block_first_bin[jb];
   const uint32_t b_start = a.bin_start[B], b_end = a.bin_start[B + 1];
   if (!(b_start < rs && b_start >= rs_prev)) return;     // not cut here, or cut at an earlier boundary
   const uint32_t j0 = (uint32_t)jb - 1;
-  const uint32_t j1 = (uint32_t)(((uint64_t)b_end * Ge + T - 1) / T - 1);
+  uint32_t j1 = (uint32_t)jb;                            // the last block whose range reaches into the bin
+  while (j1 + 1 < Ge && a.block_start[j1 + 1] < b_end) ++j1;
   const float vmax = __uint_as_float(*a.rec_max_bits);
   int ev, ec;
   frexpf(vmax, &ev);
@@ -1259,6 +1292,7 @@ __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
     for (int q = threadIdx.x; q < lim; q += blockDim.x) {
       long long s0 = 0, s1 = 0;
       for (uint32_t jj = j0; jj <= j1; ++jj) {
+        if (a.block_start[jj] == a.block_start[jj + 1]) continue;   // an empty range wrote no slot
         const size_t sl = 2 * (size_t)jj + (a.block_first_bin[jj] == B ? 0 : 1);
         const unsigned long long* S = a.split_acc + (sl * n_sub + sub) * (2 * NB);
         s0 += (long long)S[2 * q];
@@ -1574,10 +1608,10 @@ hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const 
 }
 
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
-                           uint32_t* bin_start, int32_t* block_first_bin, int reduce_grid, uint32_t* rec_max_bits,
-                           hipStream_t s) {
+                           uint32_t* bin_start, uint32_t* block_start, int32_t* block_first_bin, int reduce_grid,
+                           uint32_t* rec_max_bits, hipStream_t s) {
   k_bin_rowscan<<<n_bins, 256, 0, s>>>(counts, grid, rel, totals);
-  k_bin_plan<<<1, 1024, 0, s>>>(totals, n_bins, reduce_grid, bin_start, block_first_bin, rec_max_bits);
+  k_bin_plan<<<1, 1024, 0, s>>>(totals, n_bins, reduce_grid, bin_start, block_start, block_first_bin, rec_max_bits);
   return hipGetLastError();
 }
 
