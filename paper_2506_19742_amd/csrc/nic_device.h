@@ -15,14 +15,15 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kPtsPerBlock = kPtsPerWave * kWavesPerBlock;
 constexpr int kTile = 33;            // padded row length of the per-wave LDS transpose tiles
-constexpr int kBinBits = 12;         // reduction tile: 2^12 entries (64 KB of int64 x 2 in LDS)
+constexpr int kBinBits = 13;         // reduction tile: 2^13 entries (128 KB of int64 x 2 in LDS)
 // A table-gradient bin spans 2^bin_shift entries, bin_shift >= kBinBits, chosen per model so that
 // the per-bin histogram fits in LDS beside the kernels' own tiles; a bin of more than one tile is
 // reduced tile by tile.
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kReduceThreads = 1024;  // threads of a bin-reduction block
 constexpr int kBinTilePer = (1 << kBinBits) / kReduceThreads;  // tile entries per thread
-constexpr unsigned kFlushCost = 16384;  // a tile flush costs about as much time as streaming this many records
+constexpr unsigned kFlushCost = 32768;
+constexpr int kCombineParts = 4;       // k_bin_combine blocks per cut bin (each takes a quarter of every tile)  // a tile flush costs about as much time as streaming this many records
 
 // One corner contribution to the table gradient: entry and the two feature gradients.
 struct BinRec {

@@ -1238,23 +1238,26 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
 
 // Bins cut by the range boundaries of k_bin_reduce: block j (1 <= j < G') takes the bin holding
 // record block_start[j] when that bin starts inside block j - 1's range, adds the int64 slots of the
-// blocks j0 = j - 1 .. j1 that hold part of it in order, and adds the result to the FP32 gradient.  The grid is the reduction's
-// grid G followed by a.dense_blocks blocks of the dense gradient reduction.
+// blocks j0 = j - 1 .. j1 that hold part of it in order, and adds the result to the FP32 gradient.
+// Each such block j is kCombineParts blocks here, part k taking the k-th part of every tile (short
+// chains of loads per thread instead of eight entries each), and the grid is kCombineParts x the
+// reduction's grid G followed by a.dense_blocks blocks of the dense gradient reduction.
 __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
-  constexpr int NB = 1 << kBinBits;
+  constexpr int NB = 1 << kBinBits, QP = NB / kCombineParts;
   __shared__ float red[1024];
-  const int G = gridDim.x - a.dense_blocks;
-  if ((int)blockIdx.x >= G) {   // block-uniform
-    dense_reduce_block(a.dense, blockIdx.x - G, red);
+  const int GP = gridDim.x - a.dense_blocks, G = GP / kCombineParts;
+  if ((int)blockIdx.x >= GP) {   // block-uniform
+    dense_reduce_block(a.dense, blockIdx.x - GP, red);
     return;
   }
+  const int part = blockIdx.x % kCombineParts, q0 = part * QP;
   if (a.fused) {   // bins without records: Adam with a zero gradient (dense Adam semantics)
-    for (int B = blockIdx.x; B < a.n_bins; B += G) {
+    for (int B = blockIdx.x / kCombineParts; B < a.n_bins; B += G) {
       if (a.bin_start[B] != a.bin_start[B + 1]) continue;
       for (int sub = 0; sub < a.n_sub; ++sub) {
         const uint32_t base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
         const int64_t lim = min((int64_t)NB, a.n_entries - (int64_t)base);
-        for (int q = threadIdx.x; q < lim; q += blockDim.x) {
+        for (int q = q0 + threadIdx.x; q < min((int64_t)(q0 + QP), lim); q += blockDim.x) {
           float2 pp = reinterpret_cast<float2*>(a.p)[base + q], mm = reinterpret_cast<float2*>(a.m)[base + q],
                  vv = reinterpret_cast<float2*>(a.v)[base + q];
           adam_update(pp.x, mm.x, vv.x, 0.0f, a.adam);
@@ -1269,7 +1272,7 @@ __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
   }
   const uint64_t T = a.bin_start[a.n_bins];
   const uint64_t Ge = T < (uint64_t)G ? T : (uint64_t)G;
-  const uint64_t jb = blockIdx.x;
+  const uint64_t jb = blockIdx.x / kCombineParts;
   if (jb == 0 || jb >= Ge) return;
   const uint32_t rs = a.block_start[jb], rs_prev = a.block_start[jb - 1];
   if (rs >= T) return;
@@ -1289,7 +1292,7 @@ __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
     const uint32_t base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
     const int64_t lim = min((int64_t)NB, a.n_entries - (int64_t)base);
     float2* g2 = reinterpret_cast<float2*>(a.grad_table) + base;
-    for (int q = threadIdx.x; q < lim; q += blockDim.x) {
+    for (int q = q0 + threadIdx.x; q < min((int64_t)(q0 + QP), lim); q += blockDim.x) {
       long long s0 = 0, s1 = 0;
       for (uint32_t jj = j0; jj <= j1; ++jj) {
         if (a.block_start[jj] == a.block_start[jj + 1]) continue;   // an empty range wrote no slot
@@ -1623,7 +1626,7 @@ hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s) {
   if (a.dense_blocks != (a.dense.nd + 63) / 64) return hipErrorInvalidValue;
   if (a.fused) k_bin_reduce<true><<<grid, kReduceThreads, bin_reduce_lds(), s>>>(a);
   else k_bin_reduce<false><<<grid, kReduceThreads, bin_reduce_lds(), s>>>(a);
-  k_bin_combine<<<grid + a.dense_blocks, 1024, 0, s>>>(a);
+  k_bin_combine<<<kCombineParts * grid + a.dense_blocks, 1024, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -78,12 +78,13 @@ def test_voxel_step_matches_oracle(ora):
 
 
 def test_voxel_step_wide_bins_matches_oracle(ora):
-    """Four 256^3-workload tables at width 64: bins of 2^14 entries, each reduced over 4 LDS tiles."""
+    """Four 256^3-workload tables at width 64: bins of 2^14 entries, wider than the bin reduction's
+    2^13-entry LDS tile, so each bin is reduced tile by tile."""
     K = 4
     w = synth.WORKLOADS["ct256"]
     cfg = nic.config_for(w, n_tables=K, mlp_width=64, seed=11)
     lay = nic.nic_describe(cfg)
-    assert lay["bin_shift"] > 12
+    assert lay["bin_shift"] > 13
     oc = ora.Config(n_levels=cfg.n_levels, feats=2, log2_table=cfg.log2_table, base_res=cfg.base_res,
                     max_res=cfg.max_res, depth=cfg.mlp_depth, width=cfg.mlp_width)
     print(f"[case] K={K} W=64 bin_shift={lay['bin_shift']} creating model", flush=True)
