@@ -95,7 +95,7 @@ typedef struct nic_layout {
   int64_t n_dense;            /* LayerNorm + MLP parameters */
   int64_t dense_offset;       /* index of the first dense parameter in the parameter vector */
   int64_t n_params_padded;    /* length of the parameter vector (padding entries stay 0) */
-  int32_t bin_shift;          /* table-gradient bins span 2^bin_shift entries (>= 12) */
+  int32_t bin_shift;          /* table-gradient bins span 2^bin_shift entries (>= 13) */
   int32_t n_bins;             /* bins over all tables */
 } nic_layout;
 
