@@ -374,6 +374,8 @@ def test_samples_follow_pixel_ray(ora):
         assert np.all(np.diff(t) > 0)                 # ordered along the ray, one per bin
         k = np.floor((t - t[0]) / delta + jit[0]).astype(int)
         assert k.tolist() == list(range(32))
+        # sample i sits at fraction jit[i] of its bin (stratified sampling with the given jitter)
+        np.testing.assert_allclose((t - t[0]) / delta, np.arange(32) + jit - jit[0], atol=1e-3)
 
 
 def test_constant_field_line_integral_closed_form(ora):
@@ -543,8 +545,7 @@ def test_finite_differences_l1_loss(ora):
 # Adam, volume rendering, PSNR, pre-training voxel loss
 # ---------------------------------------------------------------------------------------------
 
-def test_adam_first_step_closed_form():
-    import oracle as ora
+def test_adam_first_step_closed_form(ora):
     rng = np.random.default_rng(15)
     g = rng.standard_normal(1000) * np.logspace(-9, 1, 1000)
     g[::7] = 0.0
@@ -555,8 +556,7 @@ def test_adam_first_step_closed_form():
     assert np.all(p[::7] == p0[::7])
 
 
-def test_adam_matches_torch():
-    import oracle as ora
+def test_adam_matches_torch(ora):
     rng = np.random.default_rng(16)
     p0 = rng.standard_normal(257)
     tp = torch.tensor(p0.copy(), requires_grad=True)
