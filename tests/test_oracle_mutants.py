@@ -95,6 +95,25 @@ MUTANTS = [
      [("test_ssim_pins", {})]),
     ("voxel_trilinear_half_offset", "double u = (double)x[k] * (double)n - 0.5;", "double u = (double)x[k] * (double)n;",
      [("test_trilinear_reproduces_affine_and_voxels", {})]),
+    ("voxel_loss_gradient_sign", "((r > 0.0) - (r < 0.0)) / (double)B", "((r < 0.0) - (r > 0.0)) / (double)B",
+     [("test_voxel_loss_finite_differences", {})]),
+    ("layernorm_gain_gradient", "gd[o->o_lng + i] += gh[i] * st->xhat[i];", "gd[o->o_lng + i] += gh[i];",
+     [("test_field_and_gradient_match_torch", {"layernorm": 1})]),
+    ("mask_backward_dropped", "for (int i = 0; i < o->C; ++i) gx[i] *= c->mask[i];",
+     "for (int i = 0; i < o->C; ++i) gx[i] *= 1.0;",
+     [("test_channel_mask_pins", {"layernorm": 1}), ("test_channel_mask_pins", {"layernorm": 0})]),
+    ("pixel_cycle_walk_once", "while ((int64_t)y >= n_pix) y = feistel(seed, t, h, y);",
+     "if ((int64_t)y >= n_pix) y = feistel(seed, t, h, y);",
+     [("test_ray_pixels_distinct_and_in_range", {"n_pix": 1000, "R": 1000}),
+      ("test_ray_pixels_distinct_and_in_range", {"n_pix": 65, "R": 64}), ("test_ray_pixels_full_permutation", {})]),
+    ("view_epoch_length", "uint32_t e = t / (uint32_t)V, pos = t % (uint32_t)V;",
+     "uint32_t e = t / (uint32_t)(V + 1), pos = t % (uint32_t)V;",
+     [("test_view_order_visits_every_view_each_epoch", {})]),
+    ("table_init_range", "params[e] = (2.0 * u - 1.0) * 1e-4;", "params[e] = (2.0 * u - 1.0) * 1e-3;",
+     [("test_init_params_distribution", {})]),
+    ("render_voxel_corner_not_centre", "float x[3] = {(float)(((double)ix + 0.5) / (double)nx)",
+     "float x[3] = {(float)(((double)ix) / (double)nx)",
+     [("test_render_volume_matches_field", {})]),
 ]
 
 
