@@ -349,7 +349,8 @@ def test_step_consumes_pending_gradient(ora, tiny):
     assert float(c.model.tensors()[1].abs().max()) == 0.0
 
 
-@pytest.mark.parametrize("workload,precision", [("tiny64", 0), ("tiny64", 1), ("ct256", 0), ("ct256", 1)])
+@pytest.mark.parametrize("workload,precision", [("tiny64", 0), ("tiny64", 1), ("ct256", 0), ("ct256", 1),
+                                                ("ct512", 1)])
 def test_fused_step_equals_backward_then_adam(ora, workload, precision):
     """A training step runs Adam inside its reductions: in the bin reduction for bins one block
     holds, in the combine kernel for bins cut between blocks and for bins without records, and in
@@ -357,10 +358,16 @@ def test_fused_step_equals_backward_then_adam(ora, workload, precision):
     sign(A - A_gt) / R, Eq. 3) followed by the one separate Adam pass gives the same parameters,
     moments and FP16 table bit for bit: the update does not depend on which kernel runs it.  At
     ct256 this is the benchmarked step (2048 rays x 192 samples, 745 bins over 256 reduction
-    blocks), whose backward pass the paper-scale test checks against the oracle on sampled rays."""
+    blocks), whose backward pass the paper-scale test checks against the oracle on sampled rays; at
+    ct512 the largest benchmarked step (8192 rays x 320 samples, T = 2^21), against zero projections
+    (generating the 100 views of the scan would take most of the test's time)."""
     print(f"[case] fused step {workload} precision {precision}", flush=True)
     w = synth.WORKLOADS[workload]
-    ph, g, A = synth.scan(w)
+    if workload == "ct512":
+        g = synth.cone_geometry(w.n_det, w.n_views)
+        A = np.zeros((w.n_views, g.nv, g.nu), np.float32)
+    else:
+        _, g, A = synth.scan(w)
     proj = torch.tensor(A, device="cuda")
     models = []
     for _ in range(2):
