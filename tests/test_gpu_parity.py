@@ -512,10 +512,15 @@ def test_other_shapes_forward_backward(ora, N, depth, ln):
     m.close()
 
 
-def test_paper_scale_sampled_rays(ora):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_paper_scale_sampled_rays(ora, precision):
     """256^3 workload (16 levels, T = 2^19, 4x32 MLP, 192 samples): the full 2048-ray forward in the
-    launch configuration of the benchmark, checked on a sample of rays computed by the oracle."""
-    c = Case(ora, "ct256")
+    launch configuration of the benchmark, checked on a sample of rays computed by the oracle.  FP32
+    to the parity bars.  The precision form: forward to the bound of its error table; gradients by
+    the largest entry error (a ReLU decision that BF16 operands flip moves one point's whole
+    contribution, so this is not a rounding bound) and by the error in the 2-norm."""
+    c = Case(ora, "ct256", precision=precision)
+    fwd_tol, grad_tol = (FWD_TOL, GRAD_TOL) if precision == 0 else (3e-2, 0.25)
     p = random_params(ora, c.oc, 26, 0.05)
     c.set_params(p)
     pix, jit, tp, tj = _rays(c, 2048, 27)
@@ -523,7 +528,7 @@ def test_paper_scale_sampled_rays(ora):
     a = c.model.forward(v, tp, tj).cpu().numpy()
     sel = np.random.default_rng(28).choice(2048, 24, replace=False)
     _, oa, _ = ora.ray_batch(c.oc, c.g, p, float(c.g.angles[v]), c.A[v], pix[sel], jit[sel], grad=False)
-    assert rel(a[sel], oa) <= FWD_TOL
+    assert rel(a[sel], oa) <= fwd_tol
     # gradient of the sampled rays alone (dA zero elsewhere) against the oracle
     dA = np.zeros(2048, np.float32)
     dA[sel] = np.random.default_rng(29).standard_normal(24).astype(np.float32)
@@ -532,8 +537,13 @@ def test_paper_scale_sampled_rays(ora):
     g = c.grads()
     _, _, og = ora.ray_batch(c.oc, c.g, p, float(c.g.angles[v]), c.A[v], pix[sel], jit[sel], dA=dA[sel])
     nt = ora.n_params(c.oc)[1]
-    assert rel(g[:nt], og[:nt]) <= GRAD_TOL
-    assert rel(g[nt:], og[nt:]) <= GRAD_TOL
+    l2 = [float(np.linalg.norm(x - y) / np.linalg.norm(y)) for x, y in ((g[:nt], og[:nt]), (g[nt:], og[nt:]))]
+    print(f"[case] ct256 precision {precision}: table gradient max {rel(g[:nt], og[:nt]):.3g} 2-norm {l2[0]:.3g}; "
+          f"dense gradient max {rel(g[nt:], og[nt:]):.3g} 2-norm {l2[1]:.3g}", flush=True)
+    assert rel(g[:nt], og[:nt]) <= grad_tol
+    assert rel(g[nt:], og[nt:]) <= grad_tol
+    if precision:   # measured: table 0.067, dense 0.0055 (24 rays x 192 samples, random network)
+        assert max(l2) <= 0.15
     c.model.close()
 
 
