@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nic_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-GCC_FLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast-math",
+GCC_FLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
              "-shared", "-fPIC"]
 
 
@@ -59,6 +59,8 @@ def lib():
         d, f, i32, u32, i64 = (P(C.c_double), P(C.c_float), P(C.c_int32), P(C.c_uint32),
                                P(C.c_int64))
         L.ora_levels.argtypes = [P(Cfg), i32, i32, i64, i64, i64]
+        L.ora_set_threads.argtypes = [C.c_int32]
+        L.ora_get_threads.restype = C.c_int32
         L.ora_n_params.argtypes = [P(Cfg), i64, i64]
         L.ora_n_params.restype = C.c_int64
         L.ora_philox4x32_10.argtypes = [u32, u32, u32]
@@ -293,6 +295,15 @@ def field_backward(cfg: Config, params, xn, dmu):
     lib().ora_field_backward(C.byref(cfg.c()), _p(params, C.c_double), _p(xn, C.c_float),
                              xn.shape[0], _p(dmu, C.c_double), _p(g, C.c_double))
     return g
+
+
+def set_threads(n: int) -> None:
+    """Host threads of ray_batch (1 = serial; each thread takes a contiguous range of rays)."""
+    lib().ora_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().ora_get_threads())
 
 
 def ray_samples(geom, angle: float, pix: int, N: int, jitter):

@@ -33,6 +33,9 @@
  *    Philox4x32-10 (Salmon et al., SC'11) from its published definition.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -352,15 +355,18 @@ typedef struct {
   double y, mu;
 } point_state;
 
+/* Output activation (unstated in the paper).  0: mu = mu_max * sigmoid(y); 1: identity;
+ * 2: softplus log(1 + e^y), taken as PyTorch's Softplus (beta 1, threshold 20): above the threshold
+ * the output is y itself and its derivative exactly 1. */
 static double act_fwd(const ora_cfg* c, double y) {
   if (c->out_act == 1) return y;
-  if (c->out_act == 2) return (y > 30.0) ? y : log1p(exp(y));
+  if (c->out_act == 2) return (y > 20.0) ? y : log1p(exp(y));
   return c->mu_max / (1.0 + exp(-y));
 }
 
 static double act_grad(const ora_cfg* c, double y) {
   if (c->out_act == 1) return 1.0;
-  if (c->out_act == 2) return 1.0 / (1.0 + exp(-y));
+  if (c->out_act == 2) return (y > 20.0) ? 1.0 : 1.0 / (1.0 + exp(-y));
   double s = 1.0 / (1.0 + exp(-y));
   return c->mu_max * s * (1.0 - s);
 }
@@ -600,6 +606,44 @@ int ora_ray_samples(const ora_geom* g, double ang, int32_t pix, int32_t N, const
 /* Ray batch: Eq. (1) rendering, Eq. (3) L1 loss and the full backward pass                     */
 /* ------------------------------------------------------------------------------------------ */
 
+/* Host threads for ora_ray_batch (1 = serial).  Threads take contiguous ranges of rays; each
+ * accumulates its gradient into a buffer of its own, and the buffers are added to the caller's
+ * gradient in thread order, so a given thread count always gives the same sums.  The loss is summed
+ * over rays in ray order whatever the thread count. */
+static int g_threads = 1;
+
+void ora_set_threads(int32_t n) { g_threads = n < 1 ? 1 : n; }
+
+int32_t ora_get_threads(void) { return g_threads; }
+
+/* One ray r of a batch: Eq. (1) sum over its samples into a_pred[r], its residual A - A_gt into
+ * *res, and, when grad != NULL and the ray hits the box, the gradient of dA * A (dA from Eq. (3)
+ * in mode 0, given in mode 1) accumulated into grad. */
+static void ray_one(const ora_cfg* c, const ora_layout* o, const ora_geom* g, const double* params,
+                    double angle, const float* proj_view, int32_t R, const int32_t* pix, int32_t N,
+                    const float* jitter, int32_t mode, const double* dA_in, int32_t r, float* xn,
+                    point_state* st, double* a_pred, double* res, double* grad) {
+  const double* dn = params + o->n_entries * o->F;
+  double delta;
+  int hit = ora_ray_samples(g, angle, pix[r], N, jitter + (int64_t)r * N, xn, &delta);
+  double A = 0.0;
+  if (hit)
+    for (int32_t i = 0; i < N; ++i) {
+      point_forward(c, o, params, dn, xn + 3 * i, st);
+      A += st->mu * delta;
+    }
+  a_pred[r] = A;
+  const double rs = A - (double)proj_view[pix[r]];
+  *res = rs;
+  if (grad && hit) {
+    double dA = (mode == 0) ? ((rs > 0.0) - (rs < 0.0)) / (double)R : dA_in[r];
+    for (int32_t i = 0; i < N; ++i) {
+      point_forward(c, o, params, dn, xn + 3 * i, st);
+      point_backward(c, o, dn, st, dA * delta, grad, grad + o->n_entries * o->F);
+    }
+  }
+}
+
 /* Renders R rays of one view (pixel indices and per-sample jitter given) and, when grad != NULL,
  * accumulates the gradient.  mode 0: loss = mean_r |A_pred_r - A_gt_r| (Eq. 3) and
  * dA_r = sign(A_pred_r - A_gt_r)/R (sign(0) = 0); mode 1: dA is given (upstream gradient of
@@ -610,32 +654,45 @@ double ora_ray_batch(const ora_cfg* c, const ora_geom* g, const double* params, 
                      double* grad) {
   ora_layout o;
   if (make_layout(c, &o)) return NAN;
-  float* xn = (float*)malloc(sizeof(float) * 3 * (size_t)N);
-  const double* dn = params + o.n_entries * o.F;
-  point_state* st = (point_state*)malloc(sizeof(point_state));
-  double loss = 0.0;
-  for (int32_t r = 0; r < R; ++r) {
-    double delta;
-    int hit = ora_ray_samples(g, angle, pix[r], N, jitter + (int64_t)r * N, xn, &delta);
-    double A = 0.0;
-    if (hit)
-      for (int32_t i = 0; i < N; ++i) {
-        point_forward(c, &o, params, dn, xn + 3 * i, st);
-        A += st->mu * delta;
-      }
-    a_pred[r] = A;
-    double res = A - (double)proj_view[pix[r]];
-    if (mode == 0) loss += fabs(res);
-    if (grad && hit) {
-      double dA = (mode == 0) ? ((res > 0.0) - (res < 0.0)) / (double)R : dA_in[r];
-      for (int32_t i = 0; i < N; ++i) {
-        point_forward(c, &o, params, dn, xn + 3 * i, st);
-        point_backward(c, &o, dn, st, dA * delta, grad, grad + o.n_entries * o.F);
-      }
+  const int64_t np = o.n_entries * o.F + o.n_dense;
+  int nth = g_threads < R ? g_threads : (R > 0 ? R : 1);
+  double* res = (double*)malloc(sizeof(double) * (size_t)(R > 0 ? R : 1));
+  double** bufs = NULL;
+  if (grad && nth > 1) {
+    bufs = (double**)calloc((size_t)nth, sizeof(double*));
+    for (int t = 1; t < nth; ++t) {
+      bufs[t] = (double*)calloc((size_t)np, sizeof(double));
+      if (!bufs[t]) { nth = t; break; }   /* out of memory: fewer threads */
     }
   }
-  free(st);
-  free(xn);
+#pragma omp parallel num_threads(nth)
+  {
+#ifdef _OPENMP
+    const int t = omp_get_thread_num();
+#else
+    const int t = 0;
+#endif
+    const int32_t r0 = (int32_t)((int64_t)R * t / nth), r1 = (int32_t)((int64_t)R * (t + 1) / nth);
+    double* gt = (grad && t > 0) ? bufs[t] : grad;
+    float* xn = (float*)malloc(sizeof(float) * 3 * (size_t)N);
+    point_state* st = (point_state*)malloc(sizeof(point_state));
+    for (int32_t r = r0; r < r1; ++r)
+      ray_one(c, &o, g, params, angle, proj_view, R, pix, N, jitter, mode, dA_in, r, xn, st, a_pred,
+              &res[r], gt);
+    free(st);
+    free(xn);
+  }
+  if (bufs) {
+#pragma omp parallel for num_threads(nth) schedule(static)
+    for (int64_t i = 0; i < np; ++i)
+      for (int t = 1; t < nth; ++t) grad[i] += bufs[t][i];
+    for (int t = 1; t < nth; ++t) free(bufs[t]);
+    free(bufs);
+  }
+  double loss = 0.0;
+  if (mode == 0)
+    for (int32_t r = 0; r < R; ++r) loss += fabs(res[r]);
+  free(res);
   return (mode == 0) ? loss / (double)R : 0.0;
 }
 

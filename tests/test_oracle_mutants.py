@@ -79,7 +79,7 @@ MUTANTS = [
      [("test_samples_follow_pixel_ray", {})]),
     ("detector_axis_sign", "double P0 = dc0 + u * (-sa);", "double P0 = dc0 + u * sa;",
      [("test_samples_follow_pixel_ray", {})]),
-    ("l1_gradient_sign", "((res > 0.0) - (res < 0.0)) / (double)R", "((res < 0.0) - (res > 0.0)) / (double)R",
+    ("l1_gradient_sign", "((rs > 0.0) - (rs < 0.0)) / (double)R", "((rs < 0.0) - (rs > 0.0)) / (double)R",
      [("test_finite_differences_l1_loss", {})]),
     ("adam_bias_correction_dropped", "double mh = m[i] / bc1;", "double mh = m[i];",
      [("test_adam_first_step_closed_form", {}), ("test_adam_matches_torch", {})]),
@@ -114,6 +114,22 @@ MUTANTS = [
     ("render_voxel_corner_not_centre", "float x[3] = {(float)(((double)ix + 0.5) / (double)nx)",
      "float x[3] = {(float)(((double)ix) / (double)nx)",
      [("test_render_volume_matches_field", {})]),
+    ("train_adam_step_index", "(int64_t)t + 1, lr, b1, b2, eps);", "(int64_t)t + 2, lr, b1, b2, eps);",
+     [("test_train_is_the_composed_schedule", {})]),
+    ("train_view_of_next_step", "int32_t view = ora_view_for_step(seed, t, V);",
+     "int32_t view = ora_view_for_step(seed, t + 1, V);",
+     [("test_train_is_the_composed_schedule", {})]),
+    ("train_gradient_not_reset", "    memset(grad, 0, sizeof(double) * (size_t)np);\n", "\n",
+     [("test_train_is_the_composed_schedule", {})]),
+    ("softplus_threshold", "(y > 20.0) ? y : log1p(exp(y))", "(y > 2.0) ? y : log1p(exp(y))",
+     [("test_output_activations_match_torch", {"out_act": 2})]),
+    ("softplus_gradient_sign", "(y > 20.0) ? 1.0 : 1.0 / (1.0 + exp(-y))", "(y > 20.0) ? 1.0 : 1.0 / (1.0 + exp(y))",
+     [("test_output_activations_match_torch", {"out_act": 2})]),
+    ("identity_head_gradient", "if (c->out_act == 1) return 1.0;", "if (c->out_act == 1) return 0.5;",
+     [("test_output_activations_match_torch", {"out_act": 1})]),
+    ("thread_buffers_dropped", "      for (int t = 1; t < nth; ++t) grad[i] += bufs[t][i];",
+     "      for (int t = 1; t < nth; ++t) grad[i] += 0.0 * bufs[t][i];",
+     [("test_ray_batch_thread_count_invariance", {})]),
 ]
 
 

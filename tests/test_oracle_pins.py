@@ -241,7 +241,12 @@ def _torch_field(ora, cfg, params, xn, enc_idx, enc_w):
         fin = C if k == 0 else cfg.width
         h = torch.relu(F.linear(h, seg(f"W{k}", (cfg.width, fin)), seg(f"b{k}", (cfg.width,))))
     y = F.linear(h, seg("w_out", (1, cfg.width)), seg("b_out", (1,)))[:, 0]
-    mu = cfg.mu_max * torch.sigmoid(y)
+    if cfg.out_act == 1:
+        mu = y
+    elif cfg.out_act == 2:
+        mu = F.softplus(y)          # beta 1, threshold 20 (PyTorch's defaults)
+    else:
+        mu = cfg.mu_max * torch.sigmoid(y)
     return mu, p, enc, z
 
 
@@ -261,6 +266,37 @@ def test_field_and_gradient_match_torch(ora, layernorm):
     np.testing.assert_allclose(z, tz.detach().numpy(), rtol=1e-10, atol=1e-12)
     np.testing.assert_allclose(mu, tmu.detach().numpy(), rtol=1e-12, atol=1e-14)
     dmu = rng.standard_normal(64)
+    g = ora.field_backward(cfg, params, xn, dmu)
+    (tmu * torch.tensor(dmu)).sum().backward()
+    tg = tp.grad.numpy()
+    np.testing.assert_allclose(g, tg, rtol=1e-9, atol=1e-12 * np.abs(tg).max())
+
+
+@pytest.mark.parametrize("out_act", [1, 2])
+def test_output_activations_match_torch(ora, out_act):
+    """Identity and softplus heads (the alternatives to mu_max * sigmoid) against torch's identity
+    and F.softplus (beta 1, threshold 20) with autograd: the output bias is set so that the head's
+    input y straddles the softplus threshold (points on both branches)."""
+    cfg = ora.Config(**CFG_SMALL, out_act=out_act)
+    tot, nt, nd = ora.n_params(cfg)
+    rng = np.random.default_rng(25)
+    params = rng.standard_normal(tot) * 0.5
+    lay = ora.dense_layout(cfg)
+    o, n = lay["ln_g"]; params[nt + o:nt + o + n] = 1 + 0.2 * rng.standard_normal(n)
+    xn = rng.random((96, 3)).astype(np.float32)
+    _, idx, w = ora.encode(cfg, params[:nt], xn, want_idx=True)
+    # shift the head bias so that the median y sits at the softplus threshold
+    ob = nt + lay["b_out"][0]
+    params[ob] = 0.0
+    cfg0 = ora.Config(**CFG_SMALL, out_act=1)
+    y0 = ora.field(cfg0, params, xn)
+    params[ob] = 20.0 - np.median(y0)
+    mu = ora.field(cfg, params, xn)
+    tmu, tp, _, _ = _torch_field(ora, cfg, params, xn, idx, w)
+    y = y0 + params[ob]
+    assert (y > 20).sum() >= 20 and (y <= 20).sum() >= 20
+    np.testing.assert_allclose(mu, tmu.detach().numpy(), rtol=1e-13, atol=1e-15)
+    dmu = rng.standard_normal(96)
     g = ora.field_backward(cfg, params, xn, dmu)
     (tmu * torch.tensor(dmu)).sum().backward()
     tg = tp.grad.numpy()
@@ -479,6 +515,62 @@ def test_ray_batch_gradient_matches_torch(ora):
     assert loss == pytest.approx(tl.item(), rel=1e-12)
     tg = tp.grad.numpy()
     np.testing.assert_allclose(grad, tg, rtol=1e-9, atol=1e-12 * np.abs(tg).max())
+
+
+def test_ray_batch_thread_count_invariance(ora):
+    """Rays split over host threads: ray sums and the loss (summed in ray order) are bitwise the
+    serial ones, the gradient (per-thread buffers added in thread order) agrees to rounding."""
+    cfg = ora.Config(**CFG_SMALL)
+    g = _geom(32, 4)
+    A = synth.project(synth.make_phantom(1, 4), g).astype(np.float32)
+    tot, nt, nd = ora.n_params(cfg)
+    params = np.random.default_rng(26).standard_normal(tot) * 0.2
+    pix, jit = synth.ray_batch(4, g.n_pix, 37, 16)
+    out = {}
+    for th in (1, 3, 8):
+        ora.set_threads(th)
+        try:
+            out[th] = ora.ray_batch(cfg, g, params, float(g.angles[1]), A[1], pix, jit)
+        finally:
+            ora.set_threads(1)
+    l1, a1, g1 = out[1]
+    for th in (3, 8):
+        l, a, gg = out[th]
+        assert l == l1
+        np.testing.assert_array_equal(a, a1)
+        np.testing.assert_allclose(gg, g1, rtol=1e-12, atol=1e-15 * np.abs(g1).max())
+
+
+def test_train_is_the_composed_schedule(ora):
+    """ora_train over n steps equals the composition of its pinned parts: view of step t from the
+    epoch permutation, Philox pixel and jitter draws of step t, Eq. (3) batch gradient from zero,
+    then Adam with step index t + 1 (Sec. 3.1: one view per step, Adam).  Starts mid-epoch
+    (t_start = 2 of V = 3 views) so the run crosses two epoch boundaries."""
+    cfg = ora.Config(n_levels=4, log2_table=10, base_res=4, max_res=32, depth=2, width=16)
+    g = synth.cone_geometry(24, 3)
+    A = synth.project(synth.make_phantom(3, 5), g).astype(np.float32)
+    tot, nt, nd = ora.n_params(cfg)
+    rng = np.random.default_rng(27)
+    p0 = rng.standard_normal(tot) * 0.1
+    m0 = np.abs(rng.standard_normal(tot)) * 1e-4
+    v0 = np.abs(rng.standard_normal(tot)) * 1e-7
+    R, N, seed, t_start, n = 40, 16, 11, 2, 5
+    p1, m1, v1 = p0.copy(), m0.copy(), v0.copy()
+    losses = ora.train(cfg, g, g.angles, A, p1, m1, v1, t_start, n, R, N, seed)
+    p2, m2, v2 = p0.copy(), m0.copy(), v0.copy()
+    views = []
+    for k in range(n):
+        t = t_start + k
+        view = ora.view_for_step(seed, t, g.n_views)
+        views.append(view)
+        pix, jit = ora.draw_rays(seed, t, g.n_pix, R, N)
+        loss, _, grad = ora.ray_batch(cfg, g, p2, float(g.angles[view]), A[view], pix, jit)
+        assert losses[k] == loss
+        ora.adam(p2, grad, m2, v2, t + 1)
+    assert sorted(views[1:4]) == [0, 1, 2]         # steps 3..5 are one whole epoch
+    np.testing.assert_array_equal(p1, p2)
+    np.testing.assert_array_equal(m1, m2)
+    np.testing.assert_array_equal(v1, v2)
 
 
 def _fd_setup(ora):
