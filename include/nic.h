@@ -46,7 +46,7 @@ typedef int32_t nic_status;
 #define NIC_EINVAL (-1)      /* invalid argument or unsupported configuration */
 #define NIC_ENOMEM (-2)      /* workspace too small */
 #define NIC_EHIP (-3)        /* HIP runtime error (launch or copy) */
-#define NIC_ENONFINITE (-4)  /* non-finite loss read back */
+#define NIC_ENONFINITE (-4)  /* a non-finite value met (projections, loss, residual, gradient) */
 #define NIC_EVERSION (-5)    /* blob or state of another format/version/configuration */
 #define NIC_ESTATE (-6)      /* call not valid in the model's current state */
 
@@ -63,11 +63,13 @@ typedef struct nic_geometry {
 
 typedef struct nic_config {
   /* Encoder (multiresolution hash grid, Instant-NGP as cited in Sec. 1): L levels, F = 2 features
-   * per level, T = 2^log2_table entries per hashed level, resolutions N_l = floor(N_min b^l) with
-   * b = exp((ln N_max - ln N_min)/(L-1)).  Supported: L in {4, 8, 12, 16}, F == 2. */
+   * per level, T = 2^log2_table entries per hashed level (4 <= log2_table <= 26), resolutions
+   * N_l = floor(N_min b^l) with b = exp((ln N_max - ln N_min)/(L-1)), 1 <= N_min <= N_max <= 32768.
+   * Supported: L in {8, 16}, F == 2. */
   int32_t n_levels, feats_per_level, log2_table, base_res, max_res;
-  /* Network: depth hidden ReLU layers of width W (W in {32, 64}, 1 <= depth <= 8), linear head;
-   * out_act 0: mu = mu_max * sigmoid(y), 1: identity, 2: softplus. */
+  /* Network: depth hidden ReLU layers of width W, linear head.  Supported (W, depth): W = 32 with
+   * 1 <= depth <= 4, and W = 64 with depth 4.  out_act 0: mu = mu_max * sigmoid(y), 1: identity
+   * (mu = y), 2: softplus (beta 1, threshold 20: mu = y above 20).  Anything else is NIC_EINVAL. */
   int32_t mlp_depth, mlp_width, out_act;
   /* Samples per ray N (multiple of 32, 32..1024) and rays per step R (1..65536, <= pixels). */
   int32_t samples_per_ray, rays_per_step;
@@ -131,8 +133,20 @@ void nic_destroy(nic_model* m);
 const char* nic_last_error(void);
 
 /* Borrows the measured projections (device, float32 [n_views][nv][nu] line integrals) until
- * nic_destroy or the next call. */
+ * nic_destroy or the next call.  Synchronous: every value is checked first; NIC_ENONFINITE (and the
+ * previous projections stay in use) when any is NaN or infinite, NIC_EINVAL for NULL. */
 nic_status nic_set_projections(nic_model* m, const float* proj_dev);
+
+/* Non-finite values met during training.  A training call (nic_step, nic_train, nic_backward,
+ * nic_adam, nic_voxel_step, nic_voxel_train) whose step meets a NaN or infinite loss, ray residual,
+ * upstream gradient, table-gradient contribution or per-block network gradient writes no parameter,
+ * Adam moment or gradient; from then on every later step is skipped the same way (the model stays
+ * bitwise as it was before that step) until the host learns of it at the next synchronising check:
+ * nic_sync, nic_train / nic_voxel_train with loss_host != NULL, or nic_save_state.  That check returns
+ * NIC_ENONFINITE, sets the step counter back to the first skipped step, and clears the condition, so
+ * training can go on from there (for example after the projections were fixed).
+ * nic_sync: synchronises the model's stream and performs that check (NIC_OK when nothing was met). */
+nic_status nic_sync(nic_model* m);
 
 /* Device views of the parameters, gradients and Adam moments, in this order: params (float32,
  * n_params_padded), grads, adam_m, adam_v, table_f16 (float16, n_table; precision 1 only, else
@@ -157,7 +171,8 @@ nic_status nic_step(nic_model* m, int32_t view, const int32_t* pix_dev, const fl
 
 /* n_steps training steps with every draw on the device: view order a fresh permutation of the
  * views per epoch of n_views steps, pixels and jitter from Philox.  loss_host: host float32
- * [n_steps] (synchronous; NIC_ENONFINITE if any loss is not finite) or NULL (asynchronous). */
+ * [n_steps] (synchronous; NIC_ENONFINITE if any loss is not finite or a step was skipped, see
+ * nic_sync) or NULL (asynchronous; a skipped step is reported by the next check). */
 nic_status nic_train(nic_model* m, int32_t n_steps, float* loss_host);
 
 /* The view nic_train uses at step `step` (host only). */
@@ -239,15 +254,17 @@ nic_status nic_set_volumes(nic_model* m, const float* vols_dev, int32_t n);
 /* Mapping Consistency Initialization transfer (Sec. 2.1, Sec. 3.1): only the LayerNorm and MLP
  * weights move between models.  nic_export_mlp writes a host blob (header + FP32 dense block);
  * with buf == NULL it only stores the size in *bytes.  nic_import_mlp loads a blob of a model with
- * the same channel count, width, depth, output activation and LayerNorm flag into the dense block
- * and resets its Adam moments (the hash table keeps its own values).  Both synchronise the stream;
- * NIC_EVERSION for a blob of another format or shape. */
+ * the same channel count, width, depth, output activation, LayerNorm flag, output scale mu_max and
+ * LayerNorm epsilon into the dense block and resets its Adam moments (the hash table keeps its own
+ * values).  Both synchronise the stream; NIC_EVERSION for a blob of another format or network. */
 nic_status nic_export_mlp(nic_model* m, void* buf, size_t* bytes);
 nic_status nic_import_mlp(nic_model* m, const void* buf, size_t bytes);
 
 /* Checkpoint and resume: the full training state (parameters, Adam moments, step counter; the
  * device draws are counter-based, so the step and the seed define the rest) as a host blob with a
- * header naming the configuration.  nic_save_state with buf == NULL stores the size in *bytes.
+ * header naming the configuration.  nic_save_state with buf == NULL stores the size in *bytes;
+ * it returns NIC_ENONFINITE without saving when a step was skipped (see nic_sync; call again to
+ * save the state as it stands after that check).
  * nic_load_state requires the same configuration and seed (NIC_EVERSION otherwise), zeroes the
  * gradients and refreshes the FP16 table copy.  A resumed run reproduces an uninterrupted one bit
  * for bit.  Both synchronise the stream. */

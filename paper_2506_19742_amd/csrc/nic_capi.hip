@@ -80,7 +80,7 @@ struct Plan {
   KernelSet ks;
   // workspace offsets (bytes)
   int64_t o_params, o_grads, o_m, o_v, o_th, o_part, o_rays, o_wsum, o_enc, o_apred, o_absres, o_loss, o_pix;
-  int64_t o_counts, o_offs, o_recmax, o_mask, o_recs, o_totals, o_binstart, o_bfb, o_bstart, o_split;
+  int64_t o_counts, o_offs, o_recmax, o_flags, o_mask, o_recs, o_totals, o_binstart, o_bfb, o_bstart, o_split;
   int n_bins = 0;
   int64_t bytes = 0;
 };
@@ -200,6 +200,7 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
   p.o_counts = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_offs = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_recmax = take(4);
+  p.o_flags = take(2 * 4);   // [0] 1 + first step that met a non-finite value (0: none), [1] scratch count
   p.o_mask = take(32 * 4);
   p.o_recs = take(max_recs * (int64_t)sizeof(BinRec));
   p.o_split = take(2ll * kMaxReduceBlocks * n_sub * (2ll << kBinBits) * 8);
@@ -231,6 +232,8 @@ struct nic_model {
   int32_t* block_first_bin = nullptr;
   uint32_t* block_start = nullptr;   // [reduce grid + 1] record ranges of the bin reduction
   uint32_t* rec_max = nullptr;
+  uint32_t* bad_step = nullptr;   // device: 0, or 1 + the first step whose values were not finite
+  uint32_t* count = nullptr;      // device scratch counter
   BinRec* recs = nullptr;
   unsigned long long* split_acc = nullptr;
   int reduce_grid = 0;
@@ -348,7 +351,7 @@ nic_status adam(nic_model* m) {
   KTimer kt(m, 4);
   NIC_HIP(launch_adam(m->params, m->grads, m->m, m->v, m->plan.n_params_pad, (float)m->cfg.lr, (float)m->cfg.beta1,
                       (float)m->cfg.beta2, (float)m->cfg.adam_eps, (float)(1.0 / bc1), (float)(1.0 / bc2), m->th,
-                      m->plan.n_table, m->n_cu, m->stream));
+                      m->plan.n_table, m->bad_step, m->n_cu, m->stream));
   m->step = t;
   return NIC_OK;
 }
@@ -389,6 +392,7 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   b.bin_start = m->bin_start;
   b.recs = m->recs;
   b.rec_max_bits = m->rec_max;
+  b.bad_step = m->bad_step;
   {
     KTimer kt(m, 2);
     NIC_HIP(launch_bwd(pl.ks, a, b, grid, bin_lds, m->stream));
@@ -413,6 +417,7 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
     br.m = m->m;
     br.v = m->v;
     br.th = m->th;
+    br.bad_step = m->bad_step;
     DenseReduceArgs& d = br.dense;
     d.partials = m->partials;
     d.n_blocks = grid;
@@ -428,6 +433,7 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
     d.p = m->params + pl.dense_off;
     d.m = m->m + pl.dense_off;
     d.v = m->v + pl.dense_off;
+    d.bad_step = m->bad_step;
     br.dense_blocks = (d.nd + 63) / 64;
     NIC_HIP(launch_bin_reduce(br, m->reduce_grid, m->stream));
   }
@@ -476,6 +482,28 @@ nic_status voxel_train_step(nic_model* m, const float* xn, int32_t n_points, flo
 }
 
 bool model_ok(const nic_model* m) { return m != nullptr && m->ws != nullptr; }
+
+// After the stream has drained: when a training call met a non-finite value (the device skipped
+// that step's update and every later one), rolls the step counter back to that step, clears the
+// flag and returns NIC_ENONFINITE.
+nic_status take_nonfinite(nic_model* m) {
+  uint32_t f = 0;
+  NIC_HIP(hipMemcpyAsync(&f, m->bad_step, 4, hipMemcpyDeviceToHost, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  if (f == 0) return NIC_OK;
+  // the device holds the low 32 bits of the step index; the first skipped step is the latest step
+  // index <= the counter with those bits
+  const uint32_t lo = f - 1u;
+  const int64_t first = m->step - (int64_t)(uint32_t)((uint32_t)m->step - lo);
+  NIC_HIP(launch_fill(reinterpret_cast<float*>(m->bad_step), 1, 0.0f, m->n_cu, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  const int64_t skipped = m->step - first;
+  m->step = first;
+  return fail(NIC_ENONFINITE,
+              "step %lld met a non-finite value (loss, residual, upstream gradient or gradient); it and the %lld "
+              "step(s) after it were not applied, the step counter is back at %lld",
+              (long long)first, (long long)(skipped > 0 ? skipped - 1 : 0), (long long)first);
+}
 
 
 
@@ -604,6 +632,8 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   m->block_first_bin = (int32_t*)(ws + p.o_bfb);
   m->block_start = (uint32_t*)(ws + p.o_bstart);
   m->rec_max = (uint32_t*)(ws + p.o_recmax);
+  m->bad_step = (uint32_t*)(ws + p.o_flags);
+  m->count = m->bad_step + 1;
   m->mask_dev = (float*)(ws + p.o_mask);
   m->recs = (BinRec*)(ws + p.o_recs);
   m->split_acc = (unsigned long long*)(ws + p.o_split);
@@ -612,6 +642,8 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   m->sqerr = (double*)(ws + p.o_sqerr);
   *out = m;
   nic_status st = NIC_OK;
+  if (launch_fill(reinterpret_cast<float*>(m->bad_step), 2, 0.0f, m->n_cu, m->stream) != hipSuccess)
+    st = fail(NIC_EHIP, "clearing the flags failed");
   if (st == NIC_OK) st = nic_init_params(m, cfg->seed);
   if (st != NIC_OK) {
     delete m;
@@ -679,8 +711,21 @@ nic_status nic_init_params(nic_model* m, uint64_t seed) {
 
 nic_status nic_set_projections(nic_model* m, const float* proj_dev) {
   if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  if (!proj_dev) return fail(NIC_EINVAL, "projections are NULL");
+  const int64_t n = (int64_t)m->n_views * m->n_pix;
+  NIC_HIP(launch_count_nonfinite(proj_dev, n, m->count, m->n_cu, m->stream));
+  uint32_t bad = 0;
+  NIC_HIP(hipMemcpyAsync(&bad, m->count, 4, hipMemcpyDeviceToHost, m->stream));
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  if (bad) return fail(NIC_ENONFINITE, "%u of the %lld projection values are not finite", bad, (long long)n);
   m->proj = proj_dev;
   return NIC_OK;
+}
+
+nic_status nic_sync(nic_model* m) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  return take_nonfinite(m);
 }
 
 nic_status nic_tensors(nic_model* m, nic_tensor* out, int32_t* count) {
@@ -740,11 +785,12 @@ nic_status nic_train(nic_model* m, int32_t n_steps, float* loss_host) {
   if (n_steps < 0) return fail(NIC_EINVAL, "n_steps must be >= 0");
   if (!m->proj) return fail(NIC_ESTATE, "projections not set");
   bool bad = false;
+  nic_status st = NIC_OK;
   for (int32_t k0 = 0; k0 < n_steps; k0 += kLossHist) {
     const int32_t kn = std::min<int32_t>(kLossHist, n_steps - k0);
     for (int32_t k = 0; k < kn; ++k) {
       const int32_t view = nic_view_for_step(m, m->step);
-      nic_status st = rays(m, view, nullptr, m->cfg.rays_per_step, (uint32_t)m->step, nullptr, nullptr);
+      st = rays(m, view, nullptr, m->cfg.rays_per_step, (uint32_t)m->step, nullptr, nullptr);
       if (st) return st;
       st = ray_train_step(m, m->cfg.rays_per_step, nullptr, m->loss + k);
       if (st) return st;
@@ -754,6 +800,8 @@ nic_status nic_train(nic_model* m, int32_t n_steps, float* loss_host) {
       NIC_HIP(hipStreamSynchronize(m->stream));
       for (int32_t k = 0; k < kn; ++k)
         if (!std::isfinite(loss_host[k0 + k])) bad = true;
+      st = take_nonfinite(m);
+      if (st) return st;
     }
   }
   if (bad) return fail(NIC_ENONFINITE, "non-finite loss");
@@ -944,6 +992,8 @@ nic_status nic_voxel_train(nic_model* m, int32_t n_steps, int32_t n_points, floa
       NIC_HIP(hipStreamSynchronize(m->stream));
       for (int32_t k = 0; k < kn; ++k)
         if (!std::isfinite(loss_host[k0 + k])) bad = true;
+      st = take_nonfinite(m);
+      if (st) return st;
     }
   }
   if (bad) return fail(NIC_ENONFINITE, "non-finite loss");
@@ -986,6 +1036,9 @@ nic_status nic_import_mlp(nic_model* m, const void* buf, size_t bytes) {
   if (h.channels != m->plan.C || h.width != m->cfg.mlp_width || h.depth != m->cfg.mlp_depth ||
       h.out_act != m->cfg.out_act || h.layernorm != m->cfg.layernorm || h.n_dense != m->plan.n_dense)
     return fail(NIC_EVERSION, "blob of another network shape");
+  if (h.mu_max != m->cfg.mu_max || h.ln_eps != m->cfg.ln_eps)
+    return fail(NIC_EVERSION, "blob of another output scale or LayerNorm epsilon (mu_max %g, ln_eps %g)", h.mu_max,
+                h.ln_eps);
   if (bytes < sizeof h + (size_t)h.n_dense * 4) return fail(NIC_EVERSION, "blob truncated");
   NIC_HIP(hipMemcpyAsync(m->params + m->plan.dense_off, (const char*)buf + sizeof h, (size_t)h.n_dense * 4,
                          hipMemcpyHostToDevice, m->stream));
@@ -1018,6 +1071,9 @@ nic_status nic_save_state(nic_model* m, void* buf, size_t* bytes) {
     return NIC_OK;
   }
   if (*bytes < need) return fail(NIC_EINVAL, "buffer too small (%zu < %zu)", *bytes, need);
+  NIC_HIP(hipStreamSynchronize(m->stream));
+  nic_status st = take_nonfinite(m);   // the saved step counter must match the parameters
+  if (st) return st;
   StateHeader h;
   state_header(m, h);
   memcpy(buf, &h, sizeof h);

@@ -56,6 +56,7 @@ struct BwdArgs {
   BinRec* recs;          // table-gradient records grouped by bin
   float* wave_loss;      // voxel-loss mode: per-wave sum of |mu - target|
   uint32_t* rec_max_bits;  // bit pattern of the largest |record| of the step (atomic max)
+  uint32_t* bad_step;    // 0, or 1 + the first step that met a non-finite value (sticky)
 };
 
 struct RaysArgs {
@@ -101,8 +102,12 @@ hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, i
 hipError_t launch_rays(const RaysArgs& a, hipStream_t s);
 hipError_t launch_raysum(const float* wave_sum, int waves_per_ray, int n_rays, float* out, hipStream_t s);
 // Adam over all n parameters from the stored gradient (gradient reset to 0).
+// Skipped (nothing written) when *bad_step != 0.
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
-                       float eps, float ibc1, float ibc2, __half* th, int64_t n_table, int n_cu, hipStream_t s);
+                       float eps, float ibc1, float ibc2, __half* th, int64_t n_table, const uint32_t* bad_step,
+                       int n_cu, hipStream_t s);
+// Number of non-finite values among x[0 .. n) into *count (u32, overwritten).
+hipError_t launch_count_nonfinite(const float* x, int64_t n, uint32_t* count, int n_cu, hipStream_t s);
 hipError_t launch_fill(float* x, int64_t n, float val, int n_cu, hipStream_t s);
 hipError_t launch_to_half(const float* src, __half* dst, int64_t n, int n_cu, hipStream_t s);
 hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const InitArgs& ia, int n_cu,
@@ -125,6 +130,7 @@ struct DenseReduceArgs {
   float* p;                // dense parameters and Adam moments [nd]
   float* m;
   float* v;
+  const uint32_t* bad_step;  // non-zero: a non-finite value was met, no parameter or gradient is written
 };
 struct BinReduceArgs {
   const BinRec* recs;             // records grouped by bin
@@ -147,6 +153,7 @@ struct BinReduceArgs {
   float* m;
   float* v;
   __half* th;
+  const uint32_t* bad_step;       // non-zero: a non-finite value was met, nothing is written
   DenseReduceArgs dense;
   int32_t dense_blocks;           // (dense.nd + 63) / 64 extra k_bin_combine blocks
 };

@@ -17,6 +17,8 @@
 //           per-block dense partials and run Adam on LayerNorm + MLP, and form the loss.
 //  k_adam   (after a backward pass that left its gradients stored) one streaming pass over every
 //           parameter: Adam update, gradient reset to 0.
+#include <cfloat>
+
 #include "nic_device.h"
 #include "nic_internal.h"
 
@@ -163,7 +165,7 @@ __device__ __forceinline__ void encode_half(const LevelTab& T, const void* __res
 template <int L>
 __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restrict__ recs, uint32_t* cursor,
                                              const float x[3], int h, const float gx[L], bool active, int ln,
-                                             uint32_t tbase, float& vmax) {
+                                             uint32_t tbase, uint32_t& vbits) {
 #pragma unroll
   for (int j = 0; j < L / 4; ++j) {
 #pragma unroll
@@ -233,7 +235,7 @@ __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restri
       if (active && tail) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-          vmax = fmaxf(vmax, fmaxf(fabsf(v0[c]), fabsf(v1[c])));
+          vbits = max(vbits, max(__float_as_uint(fabsf(v0[c])), __float_as_uint(fabsf(v1[c]))));
           const uint32_t slot = atomicAdd(cursor + (idx[c] >> T.bin_shift), 1u);
           BinRec r;
           r.idx = idx[c];
@@ -473,6 +475,7 @@ struct Combine {
   }
 };
 
+// Output activation: 0 mu_max * sigmoid(y), 1 identity, 2 softplus (beta 1, threshold 20).
 __device__ __forceinline__ float act_fwd(int act, float mu_max, float y) {
   if (act == 1) return y;
   if (act == 2) return y > 20.0f ? y : log1pf(expf(y));
@@ -481,6 +484,7 @@ __device__ __forceinline__ float act_fwd(int act, float mu_max, float y) {
 
 __device__ __forceinline__ float act_grad(int act, float mu_max, float y) {
   if (act == 1) return 1.0f;
+  if (act == 2 && y > 20.0f) return 1.0f;   // softplus above its threshold is y itself
   const float s = 1.0f / (1.0f + expf(-y));
   if (act == 2) return s;
   return mu_max * s * (1.0f - s);
@@ -632,7 +636,8 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
 
   const int waves_per_ray = a.N / kPtsPerWave;
   const int64_t n_chunks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
-  float vmax = 0.0f;
+  uint32_t vbits = 0u;   // largest |record| as a bit pattern: NaN and inf order above every finite value
+  bool bad = false;      // a residual, upstream gradient or dense partial that is not finite
   for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
     const int64_t wave_id = chunk * kWavesPerBlock + wv;
     const int64_t p = wave_id * kPtsPerWave + n;
@@ -676,16 +681,19 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
       const float mu = act_fwd(a.out_act, a.mu_max, y);
       const float tgt = trilinear(a.vols + (size_t)tid * a.vol_n * a.vol_n * a.vol_n, a.vol_n, x);
       const float res = mu - tgt;
+      bad |= valid && !(fabsf(res) <= FLT_MAX);
       dmu_vox = valid ? (float)((res > 0.0f) - (res < 0.0f)) * b.inv_R : 0.0f;
       const float l = half_sum((h == 0 && valid) ? fabsf(res) : 0.0f);
       if (lane == 0 && wave_valid) b.wave_loss[wave_id] = l;
     } else if (wave_valid) {
       if (b.dA_in) {
         dA = b.dA_in[ray];
+        bad |= !(fabsf(dA) <= FLT_MAX);
       } else {
         float A = 0.0f;
         for (int w2 = 0; w2 < waves_per_ray; ++w2) A += a.wave_sum[ray * waves_per_ray + w2];
         const float res = A - rr.a_gt;
+        bad |= !(fabsf(res) <= FLT_MAX);
         dA = (float)((res > 0.0f) - (res < 0.0f)) * b.inv_R;
         if (i == 0 && lane == 0) {
           if (b.a_pred_out) b.a_pred_out[ray] = A;
@@ -801,16 +809,23 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
 #pragma unroll
       for (int r = 0; r < RC; ++r) gx[r] *= a.mask[chan(r, h)];
     }
-    scatter_half<L>(a.lt, b.recs, cursor, x, h, gx, valid && (rr.hit || vloss), n, tbase, vmax);
+    scatter_half<L>(a.lt, b.recs, cursor, x, h, gx, valid && (rr.hit || vloss), n, tbase, vbits);
   }
-  // Largest |record| of the step (positive floats order like their bit patterns): sets the
+  // Largest |record| of the step (non-negative floats order like their bit patterns): sets the
   // fixed-point scale of the bin reduction.
-  for (int o = 32; o >= 1; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
-  if (lane == 0) atomicMax(b.rec_max_bits, __float_as_uint(vmax));
+  for (int o = 32; o >= 1; o >>= 1) vbits = max(vbits, (uint32_t)__shfl_xor((int)vbits, o, 64));
+  if (lane == 0) atomicMax(b.rec_max_bits, vbits);
+  bad |= vbits >= 0x7F800000u;
 
   __syncthreads();
-  for (int e2 = threadIdx.x; e2 < nd_pad; e2 += blockDim.x)
-    b.partials[(size_t)blockIdx.x * nd_pad + e2] = acc[e2];
+  for (int e2 = threadIdx.x; e2 < nd_pad; e2 += blockDim.x) {
+    const float v = acc[e2];
+    bad |= !(fabsf(v) <= FLT_MAX);
+    b.partials[(size_t)blockIdx.x * nd_pad + e2] = v;
+  }
+  // A non-finite value anywhere in the step: the reductions write nothing from here on (this step
+  // and every later one) until the host reads the flag and clears it.
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicCAS(b.bad_step, 0u, a.step + 1u);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -866,7 +881,7 @@ __device__ void dense_reduce_block(const DenseReduceArgs& d, int blk, float* red
   }
   red[threadIdx.x] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  if (grp == 0 && k < d.nd) {
+  if (grp == 0 && k < d.nd && *d.bad_step == 0u) {
     float t = 0.0f;
 #pragma unroll
     for (int q = 0; q < 16; ++q) t += red[threadIdx.x + 64 * q];
@@ -900,7 +915,9 @@ __device__ void dense_reduce_block(const DenseReduceArgs& d, int blk, float* red
 // floats.
 __global__ void k_adam(float4* __restrict__ p, float4* __restrict__ g, float4* __restrict__ m,
                        float4* __restrict__ v, int64_t n4, float lr, float b1, float b2, float eps,
-                       float ibc1, float ibc2, __half* __restrict__ th, int64_t n_table) {
+                       float ibc1, float ibc2, __half* __restrict__ th, int64_t n_table,
+                       const uint32_t* __restrict__ bad_step) {
+  if (*bad_step) return;   // a non-finite value was met: the model is left as it is
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += stride) {
     float4 pp = p[q], gg = g[q], mm = m[q], vv = v[q];
@@ -920,6 +937,23 @@ __global__ void k_adam(float4* __restrict__ p, float4* __restrict__ g, float4* _
       for (int k = 0; k < 4; ++k)
         if (4 * q + k < n_table) th[4 * q + k] = __float2half_rn(P[k]);
     }
+  }
+}
+
+// Count of the values of x that are NaN or infinite (grid-stride; one atomic per block).
+__global__ void __launch_bounds__(256) k_count_nonfinite(const float* __restrict__ x, int64_t n,
+                                                         uint32_t* __restrict__ count) {
+  uint32_t c = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+    c += !(fabsf(x[q]) <= FLT_MAX);
+  for (int o = 32; o >= 1; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
+  __shared__ uint32_t part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = part[0] + part[1] + part[2] + part[3];
+    if (t) atomicAdd(count, t);
   }
 }
 
@@ -1126,6 +1160,7 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
   const uint64_t Ge = T < (uint64_t)gridDim.x ? T : (uint64_t)gridDim.x;
   const uint64_t jb = blockIdx.x;
   if (jb >= Ge) return;                                            // block-uniform
+  if (*a.bad_step) return;                                         // non-finite step: write nothing
   const uint32_t rs = a.block_start[jb], re = a.block_start[jb + 1];
   if (rs >= re) return;                                            // an empty range
   const float vmax = __uint_as_float(*a.rec_max_bits);
@@ -1250,6 +1285,7 @@ __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
     dense_reduce_block(a.dense, blockIdx.x - GP, red);
     return;
   }
+  if (*a.bad_step) return;   // non-finite step: write nothing (block-uniform)
   const int part = blockIdx.x % kCombineParts, q0 = part * QP;
   if (a.fused) {   // bins without records: Adam with a zero gradient (dense Adam semantics)
     for (int B = blockIdx.x / kCombineParts; B < a.n_bins; B += G) {
@@ -1572,8 +1608,18 @@ hipError_t launch_raysum(const float* ws, int wpr, int n_rays, float* out, hipSt
   return hipGetLastError();
 }
 
+hipError_t launch_count_nonfinite(const float* x, int64_t n, uint32_t* count, int n_cu, hipStream_t s) {
+  k_fill<<<1, 64, 0, s>>>(reinterpret_cast<float*>(count), 1, 0.0f);   // bits of 0.0f are 0
+  if (n == 0) return hipGetLastError();
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > (int64_t)n_cu * 8) blocks = (int64_t)n_cu * 8;
+  k_count_nonfinite<<<(unsigned)blocks, 256, 0, s>>>(x, n, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
-                       float eps, float ibc1, float ibc2, __half* th, int64_t n_table, int n_cu, hipStream_t s) {
+                       float eps, float ibc1, float ibc2, __half* th, int64_t n_table, const uint32_t* bad_step,
+                       int n_cu, hipStream_t s) {
   const int64_t n4 = n / 4;
   int64_t blocks = (n4 + 255) / 256;
   const int64_t cap = (int64_t)n_cu * 16;
@@ -1581,7 +1627,7 @@ hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float 
   if (blocks < 1) blocks = 1;
   k_adam<<<(unsigned)blocks, 256, 0, s>>>(reinterpret_cast<float4*>(p), reinterpret_cast<float4*>(g),
                                           reinterpret_cast<float4*>(m), reinterpret_cast<float4*>(v), n4, lr, b1,
-                                          b2, eps, ibc1, ibc2, th, n_table);
+                                          b2, eps, ibc1, ibc2, th, n_table, bad_step);
   return hipGetLastError();
 }
 

@@ -61,7 +61,7 @@ EXPORTS = ["nic_describe", "nic_workspace_size", "nic_create", "nic_destroy", "n
            "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step",
            "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr",
            "nic_save_state", "nic_load_state", "nic_field_from_features", "nic_ssim",
-           "nic_set_channel_mask", "nic_channel_spectrum"]
+           "nic_set_channel_mask", "nic_channel_spectrum", "nic_sync"]
 
 _lib = None
 
@@ -110,6 +110,7 @@ def lib():
             "nic_ssim": ([vp, vp, vp, P(C.c_int32), P(C.c_double)], C.c_int32),
             "nic_set_channel_mask": ([vp, P(C.c_float), C.c_int32], C.c_int32),
             "nic_channel_spectrum": ([vp, C.c_int32, P(C.c_float)], C.c_int32),
+            "nic_sync": ([vp], C.c_int32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -248,8 +249,15 @@ class Model:
         return tuple(out)
 
     def set_projections(self, proj):
-        self.proj = proj
+        """Borrows proj (device float32 [n_views][nv][nu]); refused (NicError, NIC_ENONFINITE) when
+        a value is not finite, and then the earlier projections stay in use."""
         _check(lib().nic_set_projections(self.h, _ptr(proj)))
+        self.proj = proj
+
+    def sync(self):
+        """Synchronises the stream; raises NicError(NIC_ENONFINITE) when a training step since the
+        last check met a non-finite value (the model was left as it was before that step)."""
+        _check(lib().nic_sync(self.h))
 
     def sync_params(self):
         _check(lib().nic_sync_params(self.h))

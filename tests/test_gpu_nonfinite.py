@@ -1,0 +1,207 @@
+"""Non-finite inputs and the output-activation alternatives, through the C ABI.
+
+A NaN or infinite value that reaches a training step (through the projections, an upstream
+gradient or a target volume) must leave the model bitwise as it was: no parameter, Adam moment,
+gradient or FP16 table entry changes, and the next synchronising call reports NIC_ENONFINITE with
+the step counter back at the first skipped step.  Projections are checked when they are set.
+The identity and softplus heads (threshold 20) are compared with the FP64 oracle like the sigmoid
+head.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2506_19742_amd import nic, synth  # noqa: E402
+from test_gpu_parity import FWD_TOL, GRAD_TOL, ocfg, random_params, rel  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _snapshot(model):
+    return [None if t is None else t.clone() for t in model.tensors()]
+
+
+def _unchanged(model, snap):
+    torch.cuda.synchronize()
+    for k, (a, b) in enumerate(zip(model.tensors(), snap)):
+        if a is None:
+            assert b is None
+            continue
+        assert torch.equal(a, b), f"tensor {k} changed"
+
+
+@pytest.fixture(scope="module", params=[0, 1], ids=["fp32", "bf16"])
+def case(request):
+    w = synth.WORKLOADS["tiny64"]
+    cfg = nic.config_for(w, seed=5, precision=request.param)
+    _, g, A = synth.scan(w)
+    print(f"[case] non-finite tiny64 precision {request.param}", flush=True)
+    m = nic.Model(cfg, g)
+    proj = torch.tensor(A, device="cuda")
+    m.set_projections(proj)
+    m.train(3, want_loss=False)                    # moments away from zero
+    m.sync()
+    yield m, proj, A, g
+    m.close()
+
+
+def test_nonfinite_projections_are_refused(case):
+    m, proj, A, g = case
+    snap = _snapshot(m)
+    for bad in (float("nan"), float("inf"), -float("inf")):
+        p2 = proj.clone()
+        p2[7, 3, 5] = bad
+        with pytest.raises(nic.NicError) as e:
+            m.set_projections(p2)
+        assert e.value.status == nic.NIC_ENONFINITE
+    _unchanged(m, snap)
+    # the earlier projections are still the ones in use
+    t0 = m.get_step()
+    losses = m.train(2)
+    assert np.all(np.isfinite(losses)) and m.get_step() == t0 + 2
+
+
+def test_nan_pixel_in_a_step_leaves_the_model_unchanged(case):
+    """The borrowed projections get one NaN after they were set: the step that draws that pixel,
+    and every later step, write nothing; nic_sync reports it and rolls the counter back."""
+    m, proj, A, g = case
+    R, N = m.cfg.rays_per_step, m.cfg.samples_per_ray
+    pix, jit = synth.ray_batch(71, g.n_pix, R, N)
+    view = 11
+    saved = proj[view].view(-1)[int(pix[3])].item()
+    snap = _snapshot(m)
+    t0 = m.get_step()
+    proj[view].view(-1)[int(pix[3])] = float("nan")
+    loss = torch.zeros(1, device="cuda")
+    m.step(view, torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda"), loss)
+    m.train(3, want_loss=False)                    # later steps are skipped too
+    m.step(view, torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda"))
+    with pytest.raises(nic.NicError) as e:
+        m.sync()
+    assert e.value.status == nic.NIC_ENONFINITE
+    assert m.get_step() == t0
+    _unchanged(m, snap)
+    assert not np.isfinite(loss.item())
+    m.sync()                                       # reported once: the condition is cleared
+    # with the pixel repaired, training goes on from the same step
+    proj[view].view(-1)[int(pix[3])] = saved
+    losses = m.train(2)
+    assert np.all(np.isfinite(losses)) and m.get_step() == t0 + 2
+
+
+def test_train_with_losses_reports_nonfinite(case):
+    m, proj, A, g = case
+    snap = _snapshot(m)
+    t0 = m.get_step()
+    saved = proj.clone()
+    proj.fill_(float("inf"))
+    with pytest.raises(nic.NicError) as e:
+        m.train(3)
+    assert e.value.status == nic.NIC_ENONFINITE
+    assert m.get_step() == t0
+    _unchanged(m, snap)
+    proj.copy_(saved)
+    m.train(1)
+    assert m.get_step() == t0 + 1
+
+
+def test_nonfinite_upstream_gradient_skips_backward_and_adam(case):
+    m, proj, A, g = case
+    R, N = m.cfg.rays_per_step, m.cfg.samples_per_ray
+    pix, jit = synth.ray_batch(72, g.n_pix, 100, N)
+    tp, tj = torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda")
+    m.zero_grad()
+    snap = _snapshot(m)
+    t0 = m.get_step()
+    dA = torch.ones(100, device="cuda")
+    dA[17] = float("nan")
+    m.backward(4, tp, tj, dA)
+    m.adam()
+    with pytest.raises(nic.NicError) as e:
+        m.sync()
+    assert e.value.status == nic.NIC_ENONFINITE
+    assert m.get_step() == t0
+    _unchanged(m, snap)
+
+
+def test_save_state_refuses_until_reported(case):
+    m, proj, A, g = case
+    snap = _snapshot(m)
+    t0 = m.get_step()
+    saved = proj.clone()
+    proj.fill_(float("nan"))
+    m.train(2, want_loss=False)
+    with pytest.raises(nic.NicError) as e:
+        m.save_state()
+    assert e.value.status == nic.NIC_ENONFINITE
+    blob = m.save_state()                          # after the report: the unchanged state
+    proj.copy_(saved)
+    _unchanged(m, snap)
+    assert m.get_step() == t0
+    m.load_state(blob)
+    assert m.get_step() == t0
+    _unchanged(m, snap)
+
+
+def test_nonfinite_target_volume_in_a_voxel_step():
+    w = synth.WORKLOADS["tiny64"]
+    cfg = nic.config_for(w, seed=8, rays_per_step=64)
+    g = synth.cone_geometry(w.n_det, w.n_views)
+    print("[case] non-finite voxel step", flush=True)
+    m = nic.Model(cfg, g)
+    vols = torch.rand((1, 16, 16, 16), device="cuda") * 0.05
+    m.set_volumes(vols)
+    m.voxel_train(2, 2048, want_loss=False)
+    m.sync()
+    snap = _snapshot(m)
+    t0 = m.get_step()
+    vols[0, 3:13, 3:13, 3:13] = float("nan")
+    with pytest.raises(nic.NicError) as e:
+        m.voxel_train(2, 2048)
+    assert e.value.status == nic.NIC_ENONFINITE
+    assert m.get_step() == t0
+    _unchanged(m, snap)
+    m.close()
+
+
+@pytest.mark.parametrize("out_act", [1, 2], ids=["identity", "softplus"])
+def test_output_activation_step_matches_oracle(ora, out_act):
+    """Identity and softplus heads: query, ray sums, loss and the post-Adam parameters of two steps
+    against the oracle.  The head bias puts the head input around the softplus threshold (20), so
+    both of its branches are taken."""
+    w = synth.WORKLOADS["tiny64"]
+    cfg = nic.config_for(w, seed=9, out_act=out_act, rays_per_step=256)
+    _, g, A = synth.scan(w)
+    print(f"[case] out_act {out_act}", flush=True)
+    m = nic.Model(cfg, g)
+    m.set_projections(torch.tensor(A, device="cuda"))
+    oc = ocfg(ora, cfg)
+    p = random_params(ora, oc, 73, 0.05)
+    lay = ora.dense_layout(oc)
+    tot, nt, nd = ora.n_params(oc)
+    xq = np.random.default_rng(74).random((4096, 3)).astype(np.float32)
+    if out_act == 2:
+        p[nt + lay["b_out"][0]] = 0.0
+        y0 = ora.field(ora.Config(**{**oc.__dict__, "out_act": 1}), p, xq)
+        p[nt + lay["b_out"][0]] = np.float32(20.0 - np.median(y0))
+        y = y0 + p[nt + lay["b_out"][0]]
+        assert (y > 20).sum() > 500 and (y <= 20).sum() > 500
+    m.load_params(p)
+    mu = m.query(torch.tensor(xq, device="cuda")).cpu().numpy()
+    assert rel(mu, ora.field(oc, p, xq)) <= FWD_TOL
+    op, om, ov = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    loss = torch.zeros(1, device="cuda")
+    for k in range(2):
+        pix, jit = synth.ray_batch(75 + k, g.n_pix, 256, cfg.samples_per_ray)
+        tp, tj = torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda")
+        v = 13 + 7 * k
+        a = m.forward(v, tp, tj).cpu().numpy()
+        m.step(v, tp, tj, loss)
+        ol, oa, og = ora.ray_batch(oc, g, op, float(g.angles[v]), A[v], pix, jit)
+        assert rel(a, oa) <= FWD_TOL
+        assert abs(loss.item() - ol) <= FWD_TOL * abs(ol)
+        ora.adam(op, og, om, ov, k + 1)
+    m.sync()
+    assert rel(m.flat(m.tensors()[0]), op) <= GRAD_TOL
+    m.close()

@@ -632,6 +632,62 @@ def test_autograd_function_matches_oracle_and_fd(ora, tiny):
     params.requires_grad_(False)
 
 
+def test_autograd_precision_form_with_torch_optimizer(ora):
+    """Precision form (FP16 table copy, BF16 network operands) under autograd with a torch
+    optimiser: the update torch makes is seen by the next forward (the FP16 copy is refreshed),
+    no gradient stays pending, and a library step afterwards equals the same step of a fresh model
+    holding the torch-updated parameters, bit for bit.  The loss agrees with the FP64 oracle within
+    the precision form's bound."""
+    from paper_2506_19742_amd import autograd as ag
+    w = synth.WORKLOADS["tiny64"]
+    ph, g, A = synth.scan(w)
+    proj = torch.tensor(A, device="cuda")
+    cfg = nic.config_for(w, seed=35, precision=1)
+    print("[case] autograd precision form", flush=True)
+    ma, mb = nic.Model(cfg, g), nic.Model(cfg, g)
+    for m in (ma, mb):
+        m.set_projections(proj)
+    oc = ocfg(ora, cfg)
+    p = random_params(ora, oc, 36, 0.05)
+    ma.load_params(p)
+    pix, jit = synth.ray_batch(37, g.n_pix, 256, cfg.samples_per_ray)
+    tp, tj = torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda")
+    v = 9
+    params = ag.leaf_params(ma)
+    opt = torch.optim.SGD([params], lr=0.5)
+    gt = torch.tensor(A[v].ravel()[pix], device="cuda")
+    loss = (ag.render(params, ma, v, tp, tj) - gt).abs().mean()
+    ol, _, _ = ora.ray_batch(oc, g, p, float(g.angles[v]), A[v], pix, jit, grad=False)
+    assert abs(loss.item() - ol) <= 3e-2 * abs(ol)
+    loss.backward()
+    assert float(params.grad.abs().max()) > 0
+    opt.step()
+    params.requires_grad_(False)
+    assert float(ma.tensors()[1].abs().max()) == 0.0           # nothing pending in the library
+    # a fresh model holding the torch-updated parameters renders the same ray sums, bit for bit
+    mb.load_params(ma.flat(ma.tensors()[0]))
+    assert torch.equal(ma.tensors()[0], mb.tensors()[0])
+    with torch.no_grad():
+        a1 = ag.render(ma.tensors()[0], ma, v, tp, tj)
+    assert torch.equal(a1, mb.forward(v, tp, tj))
+    # and the library's own step continues from there identically (no stale gradient applied)
+    for m in (ma, mb):
+        m.step(v, tp, tj)
+        m.sync()
+    for k in range(5):
+        assert torch.equal(ma.tensors()[k], mb.tensors()[k]), k
+    ma.close()
+    mb.close()
+
+
+def test_autograd_refuses_a_foreign_parameter_tensor(tiny):
+    from paper_2506_19742_amd import autograd as ag
+    c = tiny
+    pix, jit, tp, tj = _rays(c, 16, 38)
+    with pytest.raises(ValueError):
+        ag.render(c.model.tensors()[0].clone().requires_grad_(True), c.model, 2, tp, tj)
+
+
 def test_repeated_steps_are_bitwise_reproducible(ora):
     """The whole step is deterministic (integer table-gradient sums, fixed-order dense reductions)."""
     w = synth.WORKLOADS["tiny64"]
