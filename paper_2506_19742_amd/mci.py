@@ -170,6 +170,9 @@ def main(argv=None):
     ap.add_argument("--gt-seed", type=int, default=1000)
     ap.add_argument("--gt-grid", type=int, default=128)
     ap.add_argument("--seed-base", type=int, default=2000)
+    ap.add_argument("--tune-seed", type=int, default=5000,
+                    help="phantom of the calibrate stage and the stability probe: outside the "
+                         "pre-training (1000-1015) and held-out (2000-2015) seeds")
     ap.add_argument("--tag", default="")
     args = ap.parse_args(argv)
     import os
@@ -182,7 +185,7 @@ def main(argv=None):
                               layernorm=ln)
 
     if args.stage == "calibrate":
-        ph, g, A, gt = scan_workload(256, 20, 2000, 50, 256, 1e5)
+        ph, g, A, gt = scan_workload(256, 20, args.tune_seed, 50, 256, 1e5)
         log(f"calibrate: 256^3, W={args.width}, D={args.depth}, precision {args.precision}")
         r = reconstruct(cfg_for(args.precision, 7), g, A, gt, args.steps, args.eval_every, args.target, log=log)
         r["model"].close()
@@ -209,10 +212,10 @@ def main(argv=None):
         return
 
     if args.stage == "stability":
-        ph, g, A, gt = scan_workload(256, 20, args.seed_base, 50, 256, 1e5)
+        ph, g, A, gt = scan_workload(256, 20, args.tune_seed, 50, 256, 1e5)
         res = {}
         for ln in (1, 0):
-            log(f"stability probe, phantom {args.seed_base}, LayerNorm {'on' if ln else 'off'}")
+            log(f"stability probe, phantom {args.tune_seed}, LayerNorm {'on' if ln else 'off'}")
             res[f"ln{ln}"] = stability(cfg_for(0, 7, ln), g, A, gt, args.steps, args.eval_every, 1 << 16, 5, log=log)
         json.dump(res, open(f"{args.out}/stability{args.tag}.json", "w"))
         return

@@ -57,3 +57,52 @@ def test_measured_traffic_needs_matching_sources(tmp_path, monkeypatch):
     f.write_text(json.dumps(rec))
     assert bench.measured_traffic("backward", "ct256", 0) is None
 
+
+
+def _write_counter_csv(d, rows):
+    os.makedirs(os.path.join(d, "host"), exist_ok=True)
+    import csv
+    with open(os.path.join(d, "host", "run_counter_collection.csv"), "w", newline="") as f:
+        wr = csv.writer(f, quoting=csv.QUOTE_ALL)
+        wr.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        wr.writerows(rows)
+
+
+def test_pmc_summary_scales_counters_by_the_copy(tmp_path, capsys):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of each kernel, scaled so that the plain copy of
+    COPY_BYTES reads and writes COPY_BYTES; k_bin_reduce and k_bin_combine add up to one kind."""
+    kib = bench.COPY_BYTES / 1024.0
+    _write_counter_csv(tmp_path / "cf", [(1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", kib / 2)])
+    _write_counter_csv(tmp_path / "cw", [(1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", kib)])
+    _write_counter_csv(tmp_path / "f", [(1, "k_fwd<16, 32, 4, 0>", "FETCH_SIZE", 1000.0),
+                                        (2, "k_fwd<16, 32, 4, 0>", "FETCH_SIZE", 3000.0),
+                                        (3, "k_bin_reduce<true>", "FETCH_SIZE", 100.0),
+                                        (4, "k_bin_combine", "FETCH_SIZE", 50.0),
+                                        (5, "k_rays", "FETCH_SIZE", 7.0)])
+    _write_counter_csv(tmp_path / "w", [(1, "k_fwd<16, 32, 4, 0>", "WRITE_SIZE", 10.0),
+                                        (3, "k_bin_reduce<true>", "WRITE_SIZE", 20.0)])
+    out = tmp_path / "traffic.json"
+    bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"),
+                      "ct256", 0, out_json=str(out))
+    t = json.load(open(out))
+    assert t["source_sha"] == bench.kernel_source_sha()
+    assert t["copy_scale"]["fetch"] == pytest.approx(2.0) and t["copy_scale"]["write"] == pytest.approx(1.0)
+    k = t["workloads"]["ct256:p0"]
+    assert k["forward"]["read"] == pytest.approx(2000.0 * 1024 * 2)     # mean of two dispatches x 2
+    assert k["forward"]["write"] == pytest.approx(10.0 * 1024)
+    assert k["bin_reduce"]["read"] == pytest.approx(150.0 * 1024 * 2)
+    assert k["bin_reduce"]["bytes_per_launch"] == pytest.approx(150.0 * 1024 * 2 + 20.0 * 1024)
+    assert "rays" not in k
+    assert "| `k_fwd<16, 32, 4, 0>` |" in capsys.readouterr().out
+
+
+def test_achievable_fractions():
+    kt = {"forward": (2.0, 10), "backward": (3.0, 10), "bin_reduce": (2.0, 10), "adam": (0.0, 0)}
+    ab = {"forward": 4e8, "backward": 4e8, "bin_reduce": 7e8}
+    ceil = {"encode_fp32": {"value": 100.0, "unit": "us"}, "stream_copy": {"value": 5000.0, "unit": "GB/s"}}
+    a = bench.achievable(kt, ab, ceil, {"backward": None, "bin_reduce": None}, 0, "ct256")
+    assert a["encode"]["frac"] == pytest.approx(100.0 / 200.0)
+    t = 0.3e-3 + 0.2e-3
+    assert a["scatter"]["frac"] == pytest.approx(1.1e9 / t / 1e9 / 5000.0)
+    assert "measured_frac" not in a["scatter"]
+    assert "encode" not in bench.achievable(kt, ab, ceil, {}, 0, "tiny64")
