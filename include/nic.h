@@ -275,6 +275,17 @@ nic_status nic_load_state(nic_model* m, const void* buf, size_t bytes);
  * squared errors are summed in FP64 on the device; synchronous.  +inf when pred == gt. */
 nic_status nic_psnr(nic_model* m, const float* gt_dev, const float* pred_dev, int64_t n, double* psnr_host);
 
+/* nic_psnr without a model or workspace, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same PSNR of gt_dev
+ * and pred_dev (device float32 [n], on the current device), on hip_stream (a stream of the current
+ * device; NULL = its default stream); synchronous.  Allocates nothing: the per-block partial sums
+ * go to a static device array of the library (4096 pairs of doubles, 64 KB, held on each device it
+ * runs on until the process ends), one block per 65,536 voxels, so n <= 268,435,456 (a 645^3
+ * volume); a larger n returns NIC_EINVAL before any launch.  Calls on one device share the array:
+ * calls that overlap on one device race. */
+nic_status nic_psnr_noalloc(const float* gt_dev, const float* pred_dev, int64_t n, void* hip_stream,
+                            double* psnr_host);
+
 /* 3-D SSIM (the structural similarity of Wang et al. 2004, which Sec. 3.1 uses with PSNR, taken
  * over volumes): local means, variances and covariance under a separable Gaussian window (sigma 1.5,
  * 11 taps per axis, weights summing to 1), C1 = (0.01 L)^2 and C2 = (0.03 L)^2 with L = max(gt), the

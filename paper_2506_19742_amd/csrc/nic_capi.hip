@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,13 @@
 #include "nic_internal.h"
 
 using namespace nic;
+
+// Scratch of nic_psnr_noalloc, a file-scope device array (each device holds its own copy until the
+// process ends): block b of the squared-error kernel writes its (sum, max) pair at [2b, 2b + 1].
+// In host code the array's name is not a device address: host code uses only the address that
+// hipGetSymbolAddress returned for the current device (scratch_address below).
+constexpr int kNoAllocBlocks = 4096;
+static __device__ __align__(256) double scratch[2 * kNoAllocBlocks];
 
 namespace {
 
@@ -506,6 +514,29 @@ nic_status take_nonfinite(nic_model* m) {
 }
 
 
+
+// nic_psnr_noalloc: one squared-error block per kNoAllocPerBlock voxels, at most kNoAllocBlocks.
+constexpr int64_t kNoAllocPerBlock = 65536;   // voxels per block (256 threads x 256)
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up once per device.
+nic_status scratch_address(double** out) {
+  int dev = -1;
+  NIC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NIC_EINVAL, "device %d outside [0, %d)", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    NIC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(NIC_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return NIC_OK;
+}
 
 }  // namespace
 
@@ -1118,6 +1149,33 @@ nic_status nic_psnr(nic_model* m, const float* gt_dev, const float* pred_dev, in
   std::vector<double> h(2 * (size_t)nb);
   NIC_HIP(hipMemcpyAsync(h.data(), m->sqerr, h.size() * 8, hipMemcpyDeviceToHost, m->stream));
   NIC_HIP(hipStreamSynchronize(m->stream));
+  double se = 0.0, mx = -1e300;
+  for (int b = 0; b < nb; ++b) {
+    se += h[2 * b];
+    mx = std::max(mx, h[2 * b + 1]);
+  }
+  const double mse = se / (double)n;
+  *psnr_host = mse == 0.0 ? INFINITY : 10.0 * std::log10(mx * mx / mse);
+  return NIC_OK;
+}
+
+nic_status nic_psnr_noalloc(const float* gt_dev, const float* pred_dev, int64_t n, void* hip_stream,
+                            double* psnr_host) {
+  if (!gt_dev || !pred_dev || !psnr_host) return fail(NIC_EINVAL, "NULL argument");
+  if (n < 1) return fail(NIC_EINVAL, "n must be >= 1");
+  if (n > (int64_t)kNoAllocBlocks * kNoAllocPerBlock)
+    return fail(NIC_EINVAL, "n = %lld exceeds the static scratch of nic_psnr_noalloc (at most %lld voxels)",
+                (long long)n, (long long)kNoAllocBlocks * kNoAllocPerBlock);
+  double* part = nullptr;
+  const nic_status st = scratch_address(&part);
+  if (st != NIC_OK) return st;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  const int nb = (int)((n + kNoAllocPerBlock - 1) / kNoAllocPerBlock);
+  // every partial the host reads is written by this launch: nothing to clear
+  NIC_HIP(launch_sqerr(gt_dev, pred_dev, n, part, nb, stream));
+  thread_local double h[2 * kNoAllocBlocks];
+  NIC_HIP(hipMemcpyAsync(h, part, (size_t)nb * 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+  NIC_HIP(hipStreamSynchronize(stream));
   double se = 0.0, mx = -1e300;
   for (int b = 0; b < nb; ++b) {
     se += h[2 * b];

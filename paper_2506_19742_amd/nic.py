@@ -61,7 +61,7 @@ EXPORTS = ["nic_describe", "nic_workspace_size", "nic_create", "nic_destroy", "n
            "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step",
            "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr",
            "nic_save_state", "nic_load_state", "nic_field_from_features", "nic_ssim",
-           "nic_set_channel_mask", "nic_channel_spectrum", "nic_sync"]
+           "nic_set_channel_mask", "nic_channel_spectrum", "nic_sync", "nic_psnr_noalloc"]
 
 _lib = None
 
@@ -111,6 +111,7 @@ def lib():
             "nic_set_channel_mask": ([vp, P(C.c_float), C.c_int32], C.c_int32),
             "nic_channel_spectrum": ([vp, C.c_int32, P(C.c_float)], C.c_int32),
             "nic_sync": ([vp], C.c_int32),
+            "nic_psnr_noalloc": ([vp, vp, C.c_int64, vp, P(C.c_double)], C.c_int32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -197,6 +198,16 @@ def nic_workspace_size(cfg: Config, geom) -> int:
     if n == 0:
         raise NicError(NIC_EINVAL, lib().nic_last_error().decode())
     return int(n)
+
+
+def psnr_noalloc(gt, pred, stream=None) -> float:
+    """nic_psnr_noalloc: PSNR of two float32 device tensors of n <= 2^28 elements without a model
+    (the library's static device scratch; allocates nothing)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(gt.device)
+    out = C.c_double()
+    _check(lib().nic_psnr_noalloc(_ptr(gt), _ptr(pred), gt.numel(), C.c_void_p(s.cuda_stream), C.byref(out)))
+    return float(out.value)
 
 
 class Model:
