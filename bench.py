@@ -142,6 +142,20 @@ KERNEL_KIND = (("k_fwd", "forward"), ("k_bwd", "backward"), ("k_bin_reduce", "bi
                ("k_bin_combine", "bin_reduce"), ("k_adam", "adam"))
 
 
+def _short(name: str) -> str:
+    """Kernel name without return type, namespace and parameter list: k_bwd<16, 32, 4, 0>."""
+    import re
+    name = re.sub(r"^void\s+", "", name.strip())
+    name = re.sub(r"^nic::", "", name)
+    depth, out = 0, []
+    for ch in name:                      # cut at the parameter list (outside template brackets)
+        if ch == "(" and depth == 0:
+            break
+        depth += (ch == "<") - (ch == ">")
+        out.append(ch)
+    return "".join(out)
+
+
 def _csv_rows(d: str, suffix: str):
     import csv
     import glob
@@ -158,7 +172,7 @@ def _per_kernel_counter(d: str, counter: str) -> dict:
     for row in _csv_rows(d, "counter_collection.csv"):
         if row.get("Counter_Name") != counter:
             continue
-        key = (row.get("Dispatch_Id"), row.get("Kernel_Name"))
+        key = (row.get("Dispatch_Id"), _short(row.get("Kernel_Name", "")))
         per_dispatch[key] = per_dispatch.get(key, 0.0) + float(row["Counter_Value"])
     out = {}
     for (_, name), v in per_dispatch.items():
@@ -210,7 +224,7 @@ def stats_summary(d: str):
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     print("| kernel | calls | avg µs | % of GPU time |\n|---|---|---|---|")
     for r in rows:
-        print(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+        print(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
     print(f"\nKernel sources sha256[:16] at measurement: `{kernel_source_sha()}`.")
 
 

@@ -79,7 +79,7 @@ def test_pmc_summary_scales_counters_by_the_copy(tmp_path, capsys):
                                         (3, "k_bin_reduce<true>", "FETCH_SIZE", 100.0),
                                         (4, "k_bin_combine", "FETCH_SIZE", 50.0),
                                         (5, "k_rays", "FETCH_SIZE", 7.0)])
-    _write_counter_csv(tmp_path / "w", [(1, "k_fwd<16, 32, 4, 0>", "WRITE_SIZE", 10.0),
+    _write_counter_csv(tmp_path / "w", [(1, "void nic::k_fwd<16, 32, 4, 0>(nic::FwdArgs)", "WRITE_SIZE", 10.0),
                                         (3, "k_bin_reduce<true>", "WRITE_SIZE", 20.0)])
     out = tmp_path / "traffic.json"
     bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"),
