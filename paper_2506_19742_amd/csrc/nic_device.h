@@ -320,6 +320,14 @@ __device__ __forceinline__ float half_sum(float v) {
   return v;
 }
 
+// The value of v, which the compiler may not assume is the same as at any earlier point: a value
+// derived from it is computed where it is used instead of being hoisted out of a loop (and, under
+// register pressure, spilled).  Emits no instruction.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Orders this wave's LDS writes before its later LDS reads (and reads before later writes).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -172,9 +172,12 @@ __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restri
     for (int q = 0; q < 2; ++q) {
       const int lA = 4 * j + q, lB = 4 * j + 2 + q;
       if (!(((T.on >> lA) | (T.on >> lB)) & 1u)) continue;   // both levels of the pair unused: no records
-      const int32_t N = h ? T.res[lB] : T.res[lA];
-      const uint32_t off = h ? T.off[lB] : T.off[lA];
-      const uint32_t st = h ? T.stride[lB] : T.stride[lA];
+      // The half's level parameters are selected here, at each level pair: hoisted out of the chunk
+      // loop they are spilled, and every reload of a spill waits for all the record stores before it.
+      const int hq = opaque(h);
+      const int32_t N = hq ? T.res[lB] : T.res[lA];
+      const uint32_t off = hq ? T.off[lB] : T.off[lA];
+      const uint32_t st = hq ? T.stride[lB] : T.stride[lA];
       uint32_t idx[8];
       float w[8];
       uint32_t g0, g1, g2;
@@ -447,9 +450,10 @@ struct Combine {
     for (int r = 0; r < 16; ++r) S[r * kWave + lane] = d[r];
     if (lane < 32) S[1024 + lane] = brow;
     __syncthreads();
+    const int ln = opaque(lane);   // addresses recomputed here rather than hoisted and spilled
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int q = 256 * wv + 64 * k + lane;
+      const int q = 256 * wv + 64 * k + ln;
       const int r = q >> 6, l2 = q & 63, m2 = l2 & 31, h2 = l2 >> 5;
       const int col = 32 * nb + m2;
       if (col < K) acc[wbase + (32 * mb + chan(r, h2)) * K + col] += sum4(q);
