@@ -461,6 +461,30 @@ struct Combine {
     if (bbase >= 0 && wv == 1 && lane < 32) acc[bbase + 32 * mb + lane] += sum4(1024 + lane);
     __syncthreads();
   }
+  // The output unit's row sums (wo0 at wobase + m, wo1 at wobase + 32 + m when two32), the LayerNorm
+  // gain and bias row sums (lg at gbase + m, lb at bbase + m for m < nrows; none when gbase < 0) and
+  // the output bias (sc at scbase), combined in one staging round: each wave adds one of them.
+  __device__ void rows_merged(float* acc, float wo0, float wo1, bool two32, int wobase, float lg, float lb,
+                              int gbase, int bbase, int nrows, float sc, int scbase) const {
+    float* S = mine();
+    if (lane < 32) {
+      S[lane] = wo0;
+      S[32 + lane] = wo1;
+      S[64 + lane] = lg;
+      S[96 + lane] = lb;
+    }
+    if (lane == 0) S[128] = sc;
+    __syncthreads();
+    if (lane < 32) {
+      if (wv == 0) acc[wobase + lane] += sum4(lane);
+      if (wv == 1 && two32) acc[wobase + 32 + lane] += sum4(32 + lane);
+      if (wv == 2 && gbase >= 0 && lane < nrows) acc[gbase + lane] += sum4(64 + lane);
+      if (wv == 3 && gbase >= 0 && lane < nrows) acc[bbase + lane] += sum4(96 + lane);
+    } else if (wv == 0 && lane == 32) {
+      acc[scbase] += sum4(128);
+    }
+    __syncthreads();
+  }
   // Up to two vectors of 32 row sums (a at abase + m, b at bbase + m for m < nrows) and one scalar.
   __device__ void rows(float* acc, float a, int abase, float b, int bbase, int nrows, float sc, int scbase) const {
     float* S = mine();
@@ -718,13 +742,14 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
     }
     const Combine cmb{acc + nd_pad, 2 * 32 * kTile, wv, lane};
     const float sdy = half_sum(h == 0 ? dy : 0.0f);
+    // row sums of the output weights' gradient, combined across waves with the LayerNorm's below
+    float rs[W / 32];
 #pragma unroll
     for (int mb = 0; mb < W / 32; ++mb) {
       tile_put<RW>(tG, t, mb, lane);
       wave_lds_sync();
-      const float rs = tile_rowsum(tG, lane);
+      rs[mb] = tile_rowsum(tG, lane);
       wave_lds_sync();
-      cmb.rows(acc, rs, Ly::g_wo + 32 * mb, 0.0f, -1, 32, sdy, mb == 0 ? Ly::g_bo : -1);
     }
 
     // Hidden layers, last to first.  Weight gradients: per 32x32 block, the FP32 tile of the layer's
@@ -797,7 +822,7 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
       wave_lds_sync();
       const float rg = tile_rowsum(tG, lane), rb = tile_rowsum(tH, lane);
       wave_lds_sync();
-      cmb.rows(acc, rg, Ly::g_lng, rb, Ly::g_lnb, C, 0.0f, -1);
+      cmb.rows_merged(acc, rs[0], rs[W / 32 - 1], W == 64, Ly::g_wo, rg, rb, Ly::g_lng, Ly::g_lnb, C, sdy, Ly::g_bo);
       sg += xor32(sg);
       sgx += xor32(sgx);
       const float mg = sg * (1.0f / C), mgx = sgx * (1.0f / C);
@@ -805,6 +830,7 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
       for (int r = 0; r < RC; ++r)
         gx[r] = rstd * (sp[Ly::s_lng + chan(r, h)] * gz[r] - mg - xh[r] * mgx);
     } else {
+      cmb.rows_merged(acc, rs[0], rs[W / 32 - 1], W == 64, Ly::g_wo, 0.0f, 0.0f, -1, -1, 0, sdy, Ly::g_bo);
 #pragma unroll
       for (int r = 0; r < RC; ++r) gx[r] = gz[r];
     }
