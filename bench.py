@@ -290,6 +290,53 @@ def converge(n_pre: int = 16, n_heldout: int = 2, cap: int = 3000, eval_every: i
             "pretraining_seconds": t_rec + info["seconds"], "wall_seconds": time.perf_counter() - t0}
 
 
+def large(steps: int = 50, warmup: int = 10, log=None) -> dict:
+    """The largest workload on one GPU: 512^3 phantom of 40 ellipsoids, 100 views on a 512 x 512
+    detector (Poisson I0 = 1e5), 16 levels x 2 features, T = 2^21, MLP 4 x 32, 320 samples per ray,
+    8192 rays per step, precision form (BF16 MLP, FP16 table, FP32 master weights and Adam):
+    training pts/s over `steps` full steps, and forward-only inference of the full 512^3 volume."""
+    import torch
+    from paper_2506_19742_amd import nic, synth
+    w = synth.WORKLOADS["ct512"]
+    cfg = nic.config_for(w, seed=2024)
+    if log:
+        log("[bench] large: generating the 512^3 scan")
+    _, g, A = synth.scan(w)
+    model = nic.Model(cfg, g)
+    model.set_projections(torch.tensor(A, device="cuda:0"))
+    del A
+    model.train(warmup, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        model.set_timing(i % TIMING_EVERY == 0)
+        model.train(1, want_loss=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = model.kernel_times()
+    model.set_timing(False)
+    loss = float(model.train(1)[-1])
+    n = w.grid
+    vol = model.render_volume(n, n, n)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(3):
+        vol = model.render_volume(n, n, n)
+    torch.cuda.synchronize()
+    rs = (time.perf_counter() - t1) / 3
+    finite = bool(torch.isfinite(vol).all())
+    del vol
+    model.close()
+    P = w.rays * w.samples
+    return {"workload": f"{w.name}: {n}^3 phantom of {w.n_ellipsoids} ellipsoids, {w.n_views} views on "
+                        f"{w.n_det}x{w.n_det} detector, Poisson I0={w.noise_i0:g}, T=2^{w.log2_table}, "
+                        f"{w.samples} samples x {w.rays} rays, precision form",
+            "train_pts_per_s": P * steps / dt, "ms_per_step": dt * 1e3 / steps, "steps": steps,
+            "points_per_step": P, "final_loss": loss,
+            "kernels_avg_ms": {k: (ms / c if c else None) for k, (ms, c) in kt.items()},
+            "render": {"n": n, "points": n ** 3, "seconds": rs, "pts_per_s": n ** 3 / rs, "finite": finite}}
+
+
 def cpu_info() -> dict:
     """CPU model and core counts of this host (threads the oracle may use: the affinity set, at
     most 16, the CPU share of one GPU on a shared box)."""
@@ -355,6 +402,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true",
                     help="skip the seconds-to-30-dB comparison (BF16 + MCI against plain FP32)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the largest workload (512^3, precision form: training and full-volume inference)")
     ap.add_argument("--converge-pre", type=int, default=16, help="MCI pre-training phantoms")
     ap.add_argument("--converge-heldout", type=int, default=2, help="held-out phantoms per arm")
     ap.add_argument("--render", type=int, default=0,
@@ -516,6 +565,8 @@ def main():
         out["render"] = {"n": n, "points": n ** 3, "seconds": rs, "pts_per_s": n ** 3 / rs}
         del vol
     model.close()
+    if not args.no_large and w.name == "ct256":
+        out["large"] = large(log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_converge and w.name == "ct256":
         print("[bench] seconds to 30 dB: MCI pre-training, then held-out phantoms", file=sys.stderr, flush=True)
         out["converge"] = converge(args.converge_pre, args.converge_heldout,
