@@ -218,6 +218,43 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, 
     print(f"\nKernel sources sha256[:16] at measurement: `{sha}`.")
 
 
+SQ_PASSES = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY "
+             "SQ_ACTIVE_INST_VALU SQ_VALU_MFMA_BUSY_CYCLES",
+             "SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_WAIT_INST_LDS SQ_LDS_BANK_CONFLICT "
+             "SQ_INSTS_SALU SQ_ACTIVE_INST_LDS")
+
+
+def sq_summary(dir_a: str, dir_b: str, stats_dir: str, n_cu: int = 256, clock_ghz: float = 2.4):
+    """Markdown tables of two rocprofv3 --pmc passes of SQ counters (SQ_PASSES), averaged per kernel
+    launch: instructions per wave, the share of the waves' lifetime spent issuing, in s_waitcnt and
+    waiting for an issue slot or a dependency, and the matrix cores' busy share (MFMA busy cycles
+    over 4 SIMDs x n_cu x the kernel's average duration from the --stats run in stats_dir)."""
+    names = [c for p in SQ_PASSES for c in p.split()]
+    per = {}
+    for d, p in ((dir_a, SQ_PASSES[0]), (dir_b, SQ_PASSES[1])):
+        for c in p.split():
+            for k, v in _per_kernel_counter(d, c).items():
+                per.setdefault(k, {})[c] = v
+    dur = {_short(r["Name"]): float(r["AverageNs"]) for r in _csv_rows(stats_dir, "kernel_stats.csv")}
+    keep = [k for k in per if k.startswith(("k_fwd", "k_bwd", "k_bin_reduce", "k_bin_combine", "k_adam"))]
+    print("| kernel | waves | VALU instr / wave | LDS instr / wave | VMEM rd / wr per wave | issuing | s_waitcnt | "
+          "waiting to issue | matrix cores busy |\n|---|---|---|---|---|---|---|---|---|")
+    for k in sorted(keep):
+        c = per[k]
+        w, cyc = c.get("SQ_WAVES", 0.0) or 1.0, c.get("SQ_WAVE_CYCLES", 0.0) or 1.0
+        mf = c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (4 * n_cu * dur.get(k, float("nan")) * clock_ghz)
+        print(f"| `{k}` | {w:.0f} | {c.get('SQ_INSTS_VALU', 0) / w:.0f} | {c.get('SQ_INSTS_LDS', 0) / w:.0f} | "
+              f"{c.get('SQ_INSTS_VMEM_RD', 0) / w:.0f} / {c.get('SQ_INSTS_VMEM_WR', 0) / w:.0f} | "
+              f"{100 * c.get('SQ_ACTIVE_INST_ANY', 0) / cyc:.0f}% | {100 * c.get('SQ_WAIT_ANY', 0) / cyc:.0f}% | "
+              f"{100 * c.get('SQ_WAIT_INST_ANY', 0) / cyc:.0f}% | {100 * mf:.0f}% |")
+    print("\nRaw averages:\n\n| kernel | counter | value |\n|---|---|---|")
+    for k in sorted(keep):
+        for c in names:
+            if c in per[k]:
+                print(f"| `{k}` | {c} | {per[k][c]:.4g} |")
+    print(f"\nKernel sources sha256[:16] at measurement: `{kernel_source_sha()}`.")
+
+
 def stats_summary(d: str):
     """Markdown table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
     rows = list(_csv_rows(d, "kernel_stats.csv"))
@@ -415,6 +452,9 @@ def main():
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="summarise rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this workload and of "
                          "--copy-calibration into profiles/traffic.json (no GPU use) and exit")
+    ap.add_argument("--sq-summary", nargs=3, metavar=("PASS_A_DIR", "PASS_B_DIR", "STATS_DIR"),
+                    help="print the SQ counter tables of the two SQ_PASSES runs (kernel times from a --stats "
+                         "run) and exit")
     ap.add_argument("--stats-summary", metavar="DIR",
                     help="print a Markdown table of a rocprofv3 --kernel-trace --stats run and exit")
     ap.add_argument("--ubench", action="store_true",
@@ -425,6 +465,9 @@ def main():
         return
     if args.stats_summary:
         stats_summary(args.stats_summary)
+        return
+    if args.sq_summary:
+        sq_summary(*args.sq_summary)
         return
     if args.ubench:
         import subprocess
