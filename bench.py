@@ -327,6 +327,31 @@ def converge(n_pre: int = 16, n_heldout: int = 2, cap: int = 3000, eval_every: i
             "pretraining_seconds": t_rec + info["seconds"], "wall_seconds": time.perf_counter() - t0}
 
 
+def small(steps: int = 200, warmup: int = 20) -> dict:
+    """The 64^3 workload (6 ellipsoids, 50 views on a 64 x 64 detector, 8 levels, T = 2^14, MLP 3 x 32,
+    1024 rays x 64 samples; its table is L2-resident), FP32 and precision form: full-step pts/s."""
+    import torch
+    from paper_2506_19742_amd import nic, synth
+    w = synth.WORKLOADS["tiny64"]
+    _, g, A = synth.scan(w)
+    out = {"workload": f"{w.name}: {w.grid}^3 phantom of {w.n_ellipsoids} ellipsoids, {w.n_views} views on "
+                       f"{w.n_det}x{w.n_det} detector, L={w.n_levels}, T=2^{w.log2_table}, MLP {w.depth}x{w.width}, "
+                       f"{w.rays} rays x {w.samples} samples"}
+    for prec in (0, 1):
+        model = nic.Model(nic.config_for(w, seed=2024, precision=prec), g)
+        model.set_projections(torch.tensor(A, device="cuda:0"))
+        model.train(warmup, want_loss=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        model.train(steps, want_loss=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        model.close()
+        out["fp32" if prec == 0 else "precision_form"] = {"ms_per_step": dt * 1e3 / steps,
+                                                          "train_pts_per_s": w.rays * w.samples * steps / dt}
+    return out
+
+
 def large(steps: int = 50, warmup: int = 10, log=None) -> dict:
     """The largest workload on one GPU: 512^3 phantom of 40 ellipsoids, 100 views on a 512 x 512
     detector (Poisson I0 = 1e5), 16 levels x 2 features, T = 2^21, MLP 4 x 32, 320 samples per ray,
@@ -439,6 +464,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true",
                     help="skip the seconds-to-30-dB comparison (BF16 + MCI against plain FP32)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed runs of --steps steps each (no kernel events), reported beside the value")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 64^3 workload (FP32 and precision form)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the largest workload (512^3, precision form: training and full-volume inference)")
     ap.add_argument("--converge-pre", type=int, default=16, help="MCI pre-training phantoms")
@@ -523,6 +552,13 @@ def main():
     dt = time.perf_counter() - t0
     kt = model.kernel_times()
     model.set_timing(False)
+    repeats = []
+    for _ in range(args.repeats):           # the same K steps again, no kernel events
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        model.train(args.steps, want_loss=False)
+        torch.cuda.synchronize()
+        repeats.append((time.perf_counter() - t1) * 1e3 / args.steps)
     losses = model.train(1)
 
     P = w.rays * w.samples
@@ -587,6 +623,8 @@ def main():
         "kernels": per_kernel,
         "kernel_timing": f"HIP events around each kernel of every {TIMING_EVERY}th timed step",
         "final_loss": float(losses[-1]),
+        "repeats": {"ms_per_step": repeats, "median_ms": float(np.median(repeats)) if repeats else None,
+                    "note": f"{len(repeats)} further runs of {args.steps} steps, no kernel events"},
         "kernel_rooflines": kernel_rooflines,
         "ceilings": ceil,
         "achievable": achievable(kt, ab, ceil, traffic, cfg.precision, w.name),
@@ -608,6 +646,8 @@ def main():
         out["render"] = {"n": n, "points": n ** 3, "seconds": rs, "pts_per_s": n ** 3 / rs}
         del vol
     model.close()
+    if not args.no_small and w.name == "ct256":
+        out["small"] = small()
     if not args.no_large and w.name == "ct256":
         out["large"] = large(log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_converge and w.name == "ct256":
