@@ -265,7 +265,7 @@ def stats_summary(d: str):
     print(f"\nKernel sources sha256[:16] at measurement: `{kernel_source_sha()}`.")
 
 
-def converge(n_pre: int = 16, n_heldout: int = 2, cap: int = 3000, eval_every: int = 50, target: float = 30.0,
+def converge(n_pre: int = 16, n_heldout: int = 4, cap: int = 3000, eval_every: int = 50, target: float = 30.0,
              log=None) -> dict:
     """Seconds (and steps) to 30 dB PSNR on held-out 256^3 phantoms, BF16 form + Mapping Consistency
     Initialization against plain FP32 with random initialisation (Sec. 2.4, Eq. 2; Sec. 3.1), every
@@ -316,7 +316,8 @@ def converge(n_pre: int = 16, n_heldout: int = 2, cap: int = 3000, eval_every: i
         hits = [per[s][arm] for s in per if per[s][arm]["seconds"] is not None]
         summary[arm] = {"reached": f"{len(hits)}/{len(per)}",
                         "median_steps": float(np.median([h["steps"] for h in hits])) if hits else None,
-                        "median_seconds": float(np.median([h["seconds"] for h in hits])) if hits else None}
+                        "median_seconds": float(np.median([h["seconds"] for h in hits])) if hits else None,
+                        "mean_seconds": float(np.mean([h["seconds"] for h in hits])) if hits else None}
     a, b_ = summary["fp32_random"]["median_seconds"], summary["bf16_mci"]["median_seconds"]
     return {"target_db": target, "metric": "seconds of training steps to reach the target PSNR (full 256^3 render)",
             "arms": summary, "speedup_bf16_mci_vs_fp32": (a / b_) if a and b_ else None, "per_phantom": per,
@@ -471,7 +472,7 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the largest workload (512^3, precision form: training and full-volume inference)")
     ap.add_argument("--converge-pre", type=int, default=16, help="MCI pre-training phantoms")
-    ap.add_argument("--converge-heldout", type=int, default=2, help="held-out phantoms per arm")
+    ap.add_argument("--converge-heldout", type=int, default=4, help="held-out phantoms per arm")
     ap.add_argument("--render", type=int, default=0,
                     help="also time forward-only inference of the full n^3 volume (voxel centres)")
     ap.add_argument("--copy-calibration", action="store_true",
