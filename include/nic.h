@@ -298,12 +298,22 @@ nic_status nic_ssim(nic_model* m, const float* gt_dev, const float* pred_dev, co
 /* Current Adam step count (host only). */
 int64_t nic_get_step(const nic_model* m);
 
+/* Encoder placement of the ray training steps (nic_train, nic_step, nic_backward) on a model with
+ * one table.  enable != 0 (the default): a level-major encoder kernel computes the hash encoding
+ * (Sec. 2.2) and the gradient-record counts, with each XCD of the chip working on one level of the
+ * grid at a time so that the level's table stays in that XCD's L2, and the forward kernel reads
+ * the stored encoding.  enable == 0: the forward kernel gathers all levels itself.  Both give
+ * bitwise identical results (same arithmetic in the same order); the switch is for measurement and
+ * testing.  Every other pass (queries, rendering, pre-training) always uses the second form.
+ * Errors: NIC_EINVAL for a NULL model. */
+nic_status nic_set_level_major_encoder(nic_model* m, int32_t enable);
+
 /* Kernel timing for benchmarks: with enable != 0, every kernel of the training path is bracketed
  * by a pair of HIP events on the model's stream.  nic_kernel_times synchronises the stream and
- * returns, per kernel kind k (0 rays, 1 forward, 2 backward, 3 unused (the dense-gradient reduction
- * runs inside the bin reduction), 4 adam, 5 bin scan, 6 bin reduce, which includes the dense
- * reduction), the total milliseconds ms[k] and the number of launches calls[k] since timing was
- * enabled; ms and calls must hold 8 entries (*count = 7). */
+ * returns, per kernel kind k (0 rays, 1 forward, 2 backward, 3 encode (the level-major encoder),
+ * 4 adam, 5 bin scan, 6 bin reduce, which includes the dense reduction), the total milliseconds
+ * ms[k] and the number of launches calls[k] since timing was enabled; ms and calls must hold 8
+ * entries (*count = 7). */
 nic_status nic_set_timing(nic_model* m, int32_t enable);
 nic_status nic_kernel_times(nic_model* m, double* ms, int64_t* calls, int32_t* count);
 

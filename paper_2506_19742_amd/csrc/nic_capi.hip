@@ -72,7 +72,7 @@ struct StateHeader {
   int64_t step;
 };
 constexpr uint32_t kStateVersion = 1;
-constexpr int kKinds = 7;   // timed kernel kinds: rays, forward, backward, reduce, adam, bin scan, bin reduce
+constexpr int kKinds = 7;   // timed kernel kinds: rays, forward, backward, encode, adam, bin scan, bin reduce
 
 int64_t up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -89,7 +89,14 @@ struct Plan {
   // workspace offsets (bytes)
   int64_t o_params, o_grads, o_m, o_v, o_th, o_part, o_rays, o_wsum, o_enc, o_apred, o_absres, o_loss, o_pix;
   int64_t o_counts, o_offs, o_recmax, o_flags, o_mask, o_recs, o_totals, o_binstart, o_bfb, o_bstart, o_split;
+  int64_t o_edge = 0, o_ebeg = 0, o_esrc = 0;
   int n_bins = 0;
+  // Level-major encoder (k_enc): for bin b, the edge rows edge_src[edge_beg[b] .. edge_beg[b + 1])
+  // whose sum is its per-block count (2l: level l's first bin, 2l + 1: its last when that differs);
+  // none for a bin strictly inside one level.  enc_lds: bytes of the largest level's histogram.
+  std::vector<int32_t> edge_beg, edge_src;
+  size_t enc_lds = 0;
+  int64_t rec_cap = 0;   // records the record buffer holds
   int64_t bytes = 0;
 };
 
@@ -198,8 +205,31 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
     p.lt.bin_shift = sh;
     p.n_bins = (int)((ent + (1ll << sh) - 1) >> sh);
   }
+  {
+    const int sh = p.lt.bin_shift;
+    std::vector<std::vector<int32_t>> src(p.n_bins);
+    int64_t nbl_max = 1;
+    for (int l = 0; l < L; ++l) {
+      const int64_t st = p.lt.stride[l];
+      const int64_t size = st ? st * st * st : (int64_t)T;
+      const int64_t b0 = (int64_t)p.lt.off[l] >> sh, b1 = ((int64_t)p.lt.off[l] + size - 1) >> sh;
+      src[b0].push_back(2 * l);
+      if (b1 != b0) src[b1].push_back(2 * l + 1);
+      nbl_max = std::max(nbl_max, b1 - b0 + 1);
+    }
+    p.edge_beg.assign(p.n_bins + 1, 0);
+    p.edge_src.clear();
+    for (int b2 = 0; b2 < p.n_bins; ++b2) {
+      p.edge_beg[b2] = (int32_t)p.edge_src.size();
+      for (int32_t v : src[b2]) p.edge_src.push_back(v);
+    }
+    p.edge_beg[p.n_bins] = (int32_t)p.edge_src.size();
+    p.enc_lds = (size_t)nbl_max * 4;
+    if (p.enc_lds > (size_t)kLdsBytes) { err = "level histogram does not fit in LDS"; return false; }
+  }
   const int64_t max_recs = R * N * L * 8;
   if (max_recs >= (1ll << 31)) { err = "too many gradient records per step (rays x samples x levels x 8 >= 2^31)"; return false; }
+  p.rec_cap = max_recs;
   const int64_t n_sub = 1ll << (p.lt.bin_shift - kBinBits);
   p.o_totals = take((int64_t)p.n_bins * 4);
   p.o_binstart = take((int64_t)(p.n_bins + 1) * 4);
@@ -207,6 +237,9 @@ bool make_plan(const nic_config* c, const nic_geometry* g, Plan& p, std::string&
   p.o_bstart = take((int64_t)(kMaxReduceBlocks + 1) * 4);
   p.o_counts = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
   p.o_offs = take((int64_t)p.n_bins * kMaxBwdBlocks * 4);
+  p.o_edge = take(2ll * L * kMaxBwdBlocks * 4);
+  p.o_ebeg = take((int64_t)(p.n_bins + 1) * 4);
+  p.o_esrc = take((int64_t)std::max<size_t>(1, p.edge_src.size()) * 4);
   p.o_recmax = take(4);
   p.o_flags = take(2 * 4);   // [0] 1 + first step that met a non-finite value (0: none), [1] scratch count
   p.o_mask = take(32 * 4);
@@ -258,6 +291,10 @@ struct nic_model {
   std::vector<int32_t> epoch_order;
   // kernel timing (benchmarks)
   bool timing = false;
+  bool level_major = true;    // ray training steps on one table encode in k_enc
+  int64_t rec_cap = 0;        // capacity of recs (records)
+  uint32_t* edge = nullptr;
+  int32_t *ebeg = nullptr, *esrc = nullptr;
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   double ms[kKinds] = {};
@@ -379,18 +416,35 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   const int64_t chunks = (P + kPtsPerBlock - 1) / kPtsPerBlock;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, m->bwd_grid));
   const size_t bin_lds = (size_t)pl.n_bins * 4;
+  // Rays on one table: the level-major encoder k_enc computes the encoding and the record counts,
+  // and k_fwd only reads the encoding.  Otherwise k_fwd gathers and counts itself.
+  const bool lvl = m->level_major && a.mode == kModeRays && pl.n_tables == 1 && !a.feats && pl.ks.enc;
   a.enc_out = m->enc;
   a.wave_sum = m->wsum;
   a.bin_counts = m->counts;
   a.n_bins = pl.n_bins;
-  {
+  if (lvl) {
+    a.enc_grid = grid;
+    a.edge_counts = m->edge;
+    {
+      KTimer kt(m, 3);
+      NIC_HIP(launch_enc(pl.ks, a, pl.enc_lds, m->stream));
+    }
+    FwdArgs f = a;
+    f.enc_pre = m->enc;
+    f.enc_out = nullptr;
+    f.bin_counts = nullptr;
+    KTimer kt(m, 1);
+    NIC_HIP(launch_fwd(pl.ks, f, grid, 0, m->stream));
+  } else {
     KTimer kt(m, 1);
     NIC_HIP(launch_fwd(pl.ks, a, grid, bin_lds, m->stream));
   }
   {
     KTimer kt(m, 5);
     NIC_HIP(launch_bin_scan(m->counts, pl.n_bins, grid, m->offs, m->totals, m->bin_start, m->block_start,
-                            m->block_first_bin, m->reduce_grid, m->rec_max, m->stream));
+                            m->block_first_bin, m->reduce_grid, m->rec_max, lvl ? m->edge : nullptr, m->ebeg,
+                            m->esrc, m->stream));
   }
   b.enc_in = m->enc;
   b.a_pred_out = m->apred;
@@ -399,6 +453,7 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   b.bin_offsets = m->offs;
   b.bin_start = m->bin_start;
   b.recs = m->recs;
+  b.rec_cap = (uint32_t)m->rec_cap;
   b.rec_max_bits = m->rec_max;
   b.bad_step = m->bad_step;
   {
@@ -628,6 +683,8 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   if (e == hipSuccess)
     e = hipFuncSetAttribute(p.ks.bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(p.ks.bwd_lds + bin_lds));
   if (e == hipSuccess)
+    e = hipFuncSetAttribute(p.ks.enc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.enc_lds);
+  if (e == hipSuccess)
     e = hipFuncSetAttribute(bin_reduce_kernel(true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bin_reduce_lds());
   if (e == hipSuccess)
     e = hipFuncSetAttribute(bin_reduce_kernel(false), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bin_reduce_lds());
@@ -667,13 +724,21 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
   m->count = m->bad_step + 1;
   m->mask_dev = (float*)(ws + p.o_mask);
   m->recs = (BinRec*)(ws + p.o_recs);
+  m->rec_cap = p.rec_cap;
+  m->edge = (uint32_t*)(ws + p.o_edge);
+  m->ebeg = (int32_t*)(ws + p.o_ebeg);
+  m->esrc = (int32_t*)(ws + p.o_esrc);
   m->split_acc = (unsigned long long*)(ws + p.o_split);
   m->totals = (uint32_t*)(ws + p.o_totals);
   m->bin_start = (uint32_t*)(ws + p.o_binstart);
   m->sqerr = (double*)(ws + p.o_sqerr);
   *out = m;
   nic_status st = NIC_OK;
-  if (launch_fill(reinterpret_cast<float*>(m->bad_step), 2, 0.0f, m->n_cu, m->stream) != hipSuccess)
+  if (hipMemcpy(m->ebeg, p.edge_beg.data(), p.edge_beg.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      (!p.edge_src.empty() &&
+       hipMemcpy(m->esrc, p.edge_src.data(), p.edge_src.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+    st = fail(NIC_EHIP, "copying the bin tables failed");
+  if (st == NIC_OK && launch_fill(reinterpret_cast<float*>(m->bad_step), 2, 0.0f, m->n_cu, m->stream) != hipSuccess)
     st = fail(NIC_EHIP, "clearing the flags failed");
   if (st == NIC_OK) st = nic_init_params(m, cfg->seed);
   if (st != NIC_OK) {
@@ -692,6 +757,12 @@ void nic_destroy(nic_model* m) {
   }
   for (hipEvent_t e : m->ev_free) (void)hipEventDestroy(e);
   delete m;
+}
+
+nic_status nic_set_level_major_encoder(nic_model* m, int32_t enable) {
+  if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
+  m->level_major = enable != 0;
+  return NIC_OK;
 }
 
 nic_status nic_set_timing(nic_model* m, int32_t enable) {

@@ -14,6 +14,8 @@ constexpr int kPtsPerWave = 32;      // two lanes per point: lane half h = lane 
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kPtsPerBlock = kPtsPerWave * kWavesPerBlock;
+constexpr int kEncThreads = 256;     // level-major encoder: one lane per point, two chunks at once
+static_assert(kEncThreads % kPtsPerBlock == 0, "the encoder takes whole chunks");
 constexpr int kTile = 33;            // padded row length of the per-wave LDS transpose tiles
 constexpr int kBinBits = 13;         // reduction tile: 2^13 entries (128 KB of int64 x 2 in LDS)
 // A table-gradient bin spans 2^bin_shift entries, bin_shift >= kBinBits, chosen per model so that
@@ -22,8 +24,8 @@ constexpr int kBinBits = 13;         // reduction tile: 2^13 entries (128 KB of 
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kReduceThreads = 1024;  // threads of a bin-reduction block
 constexpr int kBinTilePer = (1 << kBinBits) / kReduceThreads;  // tile entries per thread
-constexpr unsigned kFlushCost = 32768;
-constexpr int kCombineParts = 4;       // k_bin_combine blocks per cut bin (each takes a quarter of every tile)  // a tile flush costs about as much time as streaming this many records
+constexpr unsigned kFlushCost = 32768;  // a tile flush costs about as much time as streaming this many records
+constexpr int kCombineParts = 4;        // k_bin_combine blocks per cut bin (each takes a quarter of every tile)
 
 // One corner contribution to the table gradient: entry and the two feature gradients.
 struct BinRec {

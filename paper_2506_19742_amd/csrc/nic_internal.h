@@ -32,10 +32,15 @@ struct FwdArgs {
   const float* xn;       // points mode [n][3]
   const float* feats;    // features mode: encoder outputs [n][2L], channel l * 2 + f
   float* enc_out;        // rays mode: raw encoding, lane-major per wave (or NULL)
+  const float* enc_pre;  // rays mode: raw encoding already computed by k_enc, same layout (or NULL)
   float* wave_sum;       // rays mode: per-wave partial sums of mu * delta
   float* mu_out;         // points / voxels mode
   uint32_t* bin_counts;  // training: [n_bins][gridDim] records per (bin, block), or NULL
   int32_t n_bins;
+  // k_enc: backward grid G, and the counts of each level's first and last bin, [2L][G] (a bin at a
+  // level boundary can hold entries of several levels; the bin scan adds these rows)
+  int32_t enc_grid;
+  uint32_t* edge_counts;
   // voxel-loss mode (pre-training): point p uses table p / pts_per_table, whose entries start at
   // (p / pts_per_table) * table_stride, and the target volume of that table
   int64_t pts_per_table;
@@ -54,6 +59,7 @@ struct BwdArgs {
   const uint32_t* bin_offsets;  // [n_bins][grid] first slot of each (bin, block) run within the bin
   const uint32_t* bin_start;    // [n_bins] first record of each bin
   BinRec* recs;          // table-gradient records grouped by bin
+  uint32_t rec_cap;      // capacity of recs: a slot at or beyond it is not written (and flagged)
   float* wave_loss;      // voxel-loss mode: per-wave sum of |mu - target|
   uint32_t* rec_max_bits;  // bit pattern of the largest |record| of the step (atomic max)
   uint32_t* bad_step;    // 0, or 1 + the first step that met a non-finite value (sticky)
@@ -88,6 +94,8 @@ struct InitArgs {
 struct KernelSet {
   const void* fwd = nullptr;
   const void* bwd = nullptr;
+  const void* enc = nullptr;
+  const void* fwd_pre = nullptr;   // k_fwd reading the encoding stored by k_enc
   size_t fwd_lds = 0, bwd_lds = 0;
   int n_dense = 0, nd_pad = 0;
   bool valid = false;
@@ -99,6 +107,9 @@ KernelSet kernel_set(int L, int W, int D, int precision);
 hipError_t launch_fwd(const KernelSet& ks, const FwdArgs& a, int max_grid, size_t extra_lds, hipStream_t s);
 hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, int grid, size_t extra_lds,
                       hipStream_t s);
+// Level-major encoder of the rays mode (a.enc_out, a.bin_counts, a.edge_counts, a.enc_grid set):
+// 8 * ceil(L / 8) * a.enc_grid blocks; lds = bytes of the largest level's bin histogram.
+hipError_t launch_enc(const KernelSet& ks, const FwdArgs& a, size_t lds, hipStream_t s);
 hipError_t launch_rays(const RaysArgs& a, hipStream_t s);
 hipError_t launch_raysum(const float* wave_sum, int waves_per_ray, int n_rays, float* out, hipStream_t s);
 // Adam over all n parameters from the stored gradient (gradient reset to 0).
@@ -113,9 +124,12 @@ hipError_t launch_to_half(const float* src, __half* dst, int64_t n, int n_cu, hi
 hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const InitArgs& ia, int n_cu,
                        hipStream_t s);
 // bin_start: [n_bins + 1]; block_start: [reduce_grid + 1] record ranges of the bin reduction's blocks.
+// edge (k_enc's counts): when not NULL, bin b with edge_beg[b] < edge_beg[b + 1] takes its per-block
+// counts as the sum of the rows edge[edge_src[k] * grid ..] for k in that range, not from counts.
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
                            uint32_t* bin_start, uint32_t* block_start, int32_t* block_first_bin, int reduce_grid,
-                           uint32_t* rec_max_bits, hipStream_t s);
+                           uint32_t* rec_max_bits, const uint32_t* edge, const int32_t* edge_beg,
+                           const int32_t* edge_src, hipStream_t s);
 // Dense (LayerNorm + MLP) gradient reduction run by the last blocks of k_bin_combine.
 struct DenseReduceArgs {
   const float* partials;   // [n_blocks][nd_pad] per-block partial sums from k_bwd

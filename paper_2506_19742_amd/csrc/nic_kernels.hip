@@ -161,11 +161,13 @@ __device__ __forceinline__ void encode_half(const LevelTab& T, const void* __res
 // Corner contributions of the channel gradients gx (same layout as encode_half) as records
 // (entry, w * g_f0, w * g_f1), each written at the next slot of this block's run for the entry's bin.
 // Consecutive samples of the ray in the same cell (runs) share their 8 corner entries: a segmented
-// scan over the half sums each run and only the run's last lane writes the 8 records.
+// scan over the half sums each run and only the run's last lane writes the 8 records.  A slot at or
+// beyond rec_cap (only if the counts of the forward pass disagreed with the records) is not written;
+// it sets vbits to the top pattern, which stops the step as a non-finite one.
 template <int L>
 __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restrict__ recs, uint32_t* cursor,
                                              const float x[3], int h, const float gx[L], bool active, int ln,
-                                             uint32_t tbase, uint32_t& vbits) {
+                                             uint32_t tbase, uint32_t rec_cap, uint32_t& vbits) {
 #pragma unroll
   for (int j = 0; j < L / 4; ++j) {
 #pragma unroll
@@ -244,7 +246,8 @@ __device__ __forceinline__ void scatter_half(const LevelTab& T, BinRec* __restri
           r.idx = idx[c];
           r.v0 = v0[c];
           r.v1 = v1[c];
-          recs[slot] = r;
+          if (slot < rec_cap) recs[slot] = r;
+          else vbits = 0xFFFFFFFFu;
         }
       }
     }
@@ -565,13 +568,14 @@ __device__ __forceinline__ void mlp_forward(const float* sp, const float* z, flo
 // ---------------------------------------------------------------------------------------------
 // Forward kernel
 // ---------------------------------------------------------------------------------------------
-template <int L, int W, int D, int P>
+// PRE: rays mode with the encoding already stored by k_enc (a.enc_pre); only the network runs.
+template <int L, int W, int D, int P, bool PRE>
 __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_fwd(const FwdArgs a) {
   constexpr int C = 2 * L, RC = C / 2, RW = W / 2;
   using Ly = Lay<C, W, D, P>;
   extern __shared__ float smem[];
   float* sp = smem;
-  uint32_t* hist = a.bin_counts ? reinterpret_cast<uint32_t*>(smem + Ly::s_n) : nullptr;
+  uint32_t* hist = (!PRE && a.bin_counts) ? reinterpret_cast<uint32_t*>(smem + Ly::s_n) : nullptr;
   stage_params<C, W, D, P>(a.dense, sp);
   if (hist)
     for (int b2 = threadIdx.x; b2 < a.n_bins; b2 += blockDim.x) hist[b2] = 0u;
@@ -587,26 +591,29 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_fwd(const FwdArgs a
     int64_t ray = 0;
     int i = 0;
     RayRec rr{};
-    if (a.mode == kModeRays && wave_valid) {
+    if ((PRE || a.mode == kModeRays) && wave_valid) {
       ray = (wave_id * kPtsPerWave) / a.N;
       i = (int)(p - ray * a.N);
       rr = a.rays[ray];
     }
-    float x[3];
-    point_position(a, p, valid, ray, i, rr, x);
-    const bool vloss = a.mode == kModeVoxelLoss;
-    const uint32_t tbase = vloss ? (uint32_t)(p / a.pts_per_table) * a.table_stride : 0u;
+    const bool vloss = !PRE && a.mode == kModeVoxelLoss;
 
     float e[RC];
-    if (a.mode == kModeFeatures) {   // given encoder outputs: register r of half h is channel chan(r, h)
+    if constexpr (PRE) {             // encoding computed by k_enc in this layout
+#pragma unroll
+      for (int r = 0; r < RC; ++r) e[r] = wave_valid ? a.enc_pre[(wave_id * RC + r) * kWave + lane] : 0.0f;
+    } else if (a.mode == kModeFeatures) {   // given encoder outputs: register r of half h is channel chan(r, h)
 #pragma unroll
       for (int r = 0; r < RC; ++r) e[r] = valid ? a.feats[p * C + chan(r, h)] : 0.0f;
     } else {
+      float x[3];
+      point_position(a, p, valid, ray, i, rr, x);
+      const uint32_t tbase = vloss ? (uint32_t)(p / a.pts_per_table) * a.table_stride : 0u;
       // the bin histogram counts exactly the records the backward pass writes (hit rays only)
       encode_half<L, P>(a.lt, a.table, x, h, e, hist != nullptr, (valid && (rr.hit || vloss)) ? hist : nullptr,
                         n, tbase);
     }
-    if (a.enc_out && wave_valid) {
+    if (!PRE && a.enc_out && wave_valid) {
 #pragma unroll
       for (int r = 0; r < RC; ++r) a.enc_out[(wave_id * RC + r) * kWave + lane] = e[r];
     }
@@ -625,7 +632,7 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_fwd(const FwdArgs a
     const float y = yp + xor32(yp) + sp[Ly::s_bo];
     const float mu = act_fwd(a.out_act, a.mu_max, y);
 
-    if (a.mode == kModeRays) {
+    if (PRE || a.mode == kModeRays) {
       float c = (h == 0 && valid) ? mu * rr.delta : 0.0f;
       c = half_sum(c);
       if (lane == 0 && wave_valid) a.wave_sum[wave_id] = c;
@@ -638,6 +645,99 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_fwd(const FwdArgs a
     for (int b2 = threadIdx.x; b2 < a.n_bins; b2 += blockDim.x)
       a.bin_counts[(size_t)b2 * gridDim.x + blockIdx.x] = hist[b2];
   }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Level-major encoder of the ray training step
+// ---------------------------------------------------------------------------------------------
+// Block (l, w) computes level l of the hash encoding (Sec. 2.2) at the points of backward block w
+// (chunks w, w + G, w + 2G, ... of kPtsPerBlock points, G = a.enc_grid), stores it where k_fwd and
+// k_bwd read it (register 4(l/4) + 2(l%2) + f of lane half (l/2)%2, as encode_half leaves it) and
+// counts the records block w of k_bwd will write for level l, per bin.
+// Placement: workgroups go to the 8 XCDs of the chip in turn (block b to XCD b mod 8), so with
+// b = 8 (phase * G + w) + x and l = x + 8 phase each XCD works on one level at a time, and that
+// level's table (4 MB at FP32, 2 MB at FP16 for T = 2^19) stays in the XCD's own L2 instead of
+// the whole table streaming through every L2.
+// One lane per point; lanes 32k .. 32k + 31 of a wave hold the 32 points of one backward wave, so
+// the runs (run_flags) and the records counted are exactly those of scatter_half.  Level l is
+// skipped (zero encoding, no records) exactly when scatter_half and encode_half skip its pair.
+// Counts: a bin strictly inside level l's entry range belongs to level l alone and its count is
+// stored at bin_counts[bin][w]; the level's first and last bins, which other levels can share, go
+// to edge_counts[2l][w] and edge_counts[2l + 1][w] (0 there when both are one bin), summed by
+// the bin scan.
+template <int L, int P>
+__global__ void __launch_bounds__(kEncThreads) k_enc(const FwdArgs a) {
+  constexpr int RC = L;   // channel registers per lane in the backward layout (C / 2)
+  extern __shared__ float smem[];
+  uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
+  const int G = a.enc_grid;
+  const int s = (int)(blockIdx.x >> 3);
+  const int ph = s / G, w = s - ph * G;
+  const int l = (int)(blockIdx.x & 7u) + 8 * ph;
+  if (l >= L) return;                                   // block-uniform, before any barrier
+  const LevelTab& T = a.lt;
+  const int32_t N = T.res[l];
+  const uint32_t off = T.off[l], st = T.stride[l];
+  const uint32_t size = st ? st * st * st : T.mask + 1u;
+  const uint32_t b0 = off >> T.bin_shift, b1 = (off + size - 1u) >> T.bin_shift;
+  const int nbl = (int)(b1 - b0) + 1;
+  const bool on = ((T.on >> l) | (T.on >> (l ^ 2))) & 1u;
+  for (int k = threadIdx.x; k < nbl; k += blockDim.x) hist[k] = 0u;
+  __syncthreads();
+
+  const int t = threadIdx.x, ln = t & 31;
+  const int hh = (l >> 1) & 1, r0 = 4 * (l >> 2) + 2 * (l & 1);
+  const int64_t n_chunks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
+  constexpr int kChunksAtOnce = kEncThreads / kPtsPerBlock;
+  for (int64_t c = w + (int64_t)(t / kPtsPerBlock) * G; c < n_chunks; c += (int64_t)kChunksAtOnce * G) {
+    const int64_t p = c * kPtsPerBlock + (t % kPtsPerBlock);
+    const bool valid = p < a.n_points;
+    int64_t ray = 0;
+    int i = 0;
+    RayRec rr{};
+    if (valid) {
+      ray = p / a.N;
+      i = (int)(p - ray * a.N);
+      rr = a.rays[ray];
+    }
+    float x[3];
+    point_position(a, p, valid, ray, i, rr, x);
+    float s0 = 0.0f, s1 = 0.0f;
+    if (on) {
+      uint32_t idx[8];
+      float wt[8];
+      uint32_t g0, g1, g2;
+      level_corners(N, off, st, T.mask, x, idx, wt, g0, g1, g2);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        float2 v;
+        if constexpr (P == 0) v = reinterpret_cast<const float2*>(a.table)[idx[k]];
+        else v = __half22float2(reinterpret_cast<const __half2*>(a.table)[idx[k]]);
+        s0 += wt[k] * v.x;
+        s1 += wt[k] * v.y;
+      }
+      bool cont, tail;
+      run_flags(g0, g1, g2, ln, cont, tail);
+      if (valid && rr.hit && tail) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) atomicAdd(hist + ((idx[k] >> T.bin_shift) - b0), 1u);
+      }
+    }
+    const int64_t wid = p / kPtsPerWave;
+    if (wid * kPtsPerWave < a.n_points) {
+      float* dst = a.enc_out + (wid * RC + r0) * kWave + ln + 32 * hh;
+      dst[0] = s0;
+      dst[kWave] = s1;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nbl; k += blockDim.x) {
+    const uint32_t v = hist[k];
+    if (k == 0) a.edge_counts[(size_t)(2 * l) * G + w] = v;
+    else if (k == nbl - 1) a.edge_counts[(size_t)(2 * l + 1) * G + w] = v;
+    else a.bin_counts[(size_t)(b0 + k) * G + w] = v;
+  }
+  if (nbl == 1 && threadIdx.x == 0) a.edge_counts[(size_t)(2 * l + 1) * G + w] = 0u;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -839,7 +939,7 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
 #pragma unroll
       for (int r = 0; r < RC; ++r) gx[r] *= a.mask[chan(r, h)];
     }
-    scatter_half<L>(a.lt, b.recs, cursor, x, h, gx, valid && (rr.hit || vloss), n, tbase, vbits);
+    scatter_half<L>(a.lt, b.recs, cursor, x, h, gx, valid && (rr.hit || vloss), n, tbase, b.rec_cap, vbits);
   }
   // Largest |record| of the step (non-negative floats order like their bit patterns): sets the
   // fixed-point scale of the bin reduction.
@@ -1022,14 +1122,24 @@ __global__ void k_init(float* __restrict__ params, int64_t n_table, int64_t dens
 // Record offsets, step 1 (one block per bin): exclusive scan of the bin's per-block counts ->
 // offsets relative to the bin's first record; the bin's total.
 __global__ void __launch_bounds__(256) k_bin_rowscan(const uint32_t* __restrict__ counts, int grid,
-                                                     uint32_t* __restrict__ rel, uint32_t* __restrict__ totals) {
+                                                     uint32_t* __restrict__ rel, uint32_t* __restrict__ totals,
+                                                     const uint32_t* __restrict__ edge,
+                                                     const int32_t* __restrict__ edge_beg,
+                                                     const int32_t* __restrict__ edge_src) {
   __shared__ uint32_t part[256];
   const int b = blockIdx.x, t = threadIdx.x;
   const int per = (grid + 255) / 256;
   const int w0 = t * per, w1 = min(grid, w0 + per);
   const uint32_t* row = counts + (size_t)b * grid;
+  const int e0 = edge ? edge_beg[b] : 0, e1 = edge ? edge_beg[b + 1] : 0;
+  auto count = [&](int w) -> uint32_t {   // a bin at a level boundary: the levels' edge rows
+    if (e0 == e1) return row[w];
+    uint32_t v = 0u;
+    for (int k = e0; k < e1; ++k) v += edge[(size_t)edge_src[k] * grid + w];
+    return v;
+  };
   uint32_t s = 0;
-  for (int w = w0; w < w1; ++w) s += row[w];
+  for (int w = w0; w < w1; ++w) s += count(w);
   part[t] = s;
   __syncthreads();
   for (int o = 1; o < 256; o <<= 1) {
@@ -1041,7 +1151,7 @@ __global__ void __launch_bounds__(256) k_bin_rowscan(const uint32_t* __restrict_
   uint32_t run = part[t] - s;
   for (int w = w0; w < w1; ++w) {
     rel[(size_t)b * grid + w] = run;
-    run += row[w];
+    run += count(w);
   }
   if (t == 255) totals[b] = part[255];
 }
@@ -1590,8 +1700,10 @@ static KernelSet make_set() {
   constexpr int C = 2 * L;
   using Ly = Lay<C, W, D, P>;
   KernelSet ks;
-  ks.fwd = reinterpret_cast<const void*>(&k_fwd<L, W, D, P>);
+  ks.fwd = reinterpret_cast<const void*>(&k_fwd<L, W, D, P, false>);
+  ks.fwd_pre = reinterpret_cast<const void*>(&k_fwd<L, W, D, P, true>);
   ks.bwd = reinterpret_cast<const void*>(&k_bwd<L, W, D, P>);
+  ks.enc = reinterpret_cast<const void*>(&k_enc<L, P>);
   ks.fwd_lds = Ly::s_n * sizeof(float);
   const int nd_pad = (Ly::g_n + 3) & ~3;
   ks.bwd_lds = (Ly::s_n + nd_pad + kWavesPerBlock * 2 * 32 * kTile) * sizeof(float);
@@ -1616,14 +1728,25 @@ hipError_t launch_fwd(const KernelSet& ks, const FwdArgs& a, int max_grid, size_
   int64_t blocks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
   if (blocks == 0) return hipSuccess;
   if (max_grid > 0 && blocks > max_grid) blocks = max_grid;
+  if (a.enc_pre && (a.mode != kModeRays || a.bin_counts || a.enc_out)) return hipErrorInvalidValue;
   void* args[] = {const_cast<FwdArgs*>(&a)};
-  return hipLaunchKernel(ks.fwd, dim3((unsigned)blocks), dim3(kBlock), args, ks.fwd_lds + extra_lds, s);
+  return hipLaunchKernel(a.enc_pre ? ks.fwd_pre : ks.fwd, dim3((unsigned)blocks), dim3(kBlock), args,
+                         ks.fwd_lds + extra_lds, s);
 }
 
 hipError_t launch_bwd(const KernelSet& ks, const FwdArgs& a, const BwdArgs& b, int grid, size_t extra_lds,
                       hipStream_t s) {
   void* args[] = {const_cast<FwdArgs*>(&a), const_cast<BwdArgs*>(&b)};
   return hipLaunchKernel(ks.bwd, dim3((unsigned)grid), dim3(kBlock), args, ks.bwd_lds + extra_lds, s);
+}
+
+hipError_t launch_enc(const KernelSet& ks, const FwdArgs& a, size_t lds, hipStream_t s) {
+  if (a.n_points == 0) return hipSuccess;
+  if (a.enc_grid < 1 || !a.enc_out || !a.bin_counts || !a.edge_counts || a.mode != kModeRays)
+    return hipErrorInvalidValue;
+  const int64_t blocks = 8ll * ((a.lt.L + 7) / 8) * a.enc_grid;
+  void* args[] = {const_cast<FwdArgs*>(&a)};
+  return hipLaunchKernel(ks.enc, dim3((unsigned)blocks), dim3(kEncThreads), args, lds, s);
 }
 
 hipError_t launch_rays(const RaysArgs& a, hipStream_t s) {
@@ -1688,8 +1811,9 @@ hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const 
 
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
                            uint32_t* bin_start, uint32_t* block_start, int32_t* block_first_bin, int reduce_grid,
-                           uint32_t* rec_max_bits, hipStream_t s) {
-  k_bin_rowscan<<<n_bins, 256, 0, s>>>(counts, grid, rel, totals);
+                           uint32_t* rec_max_bits, const uint32_t* edge, const int32_t* edge_beg,
+                           const int32_t* edge_src, hipStream_t s) {
+  k_bin_rowscan<<<n_bins, 256, 0, s>>>(counts, grid, rel, totals, edge, edge_beg, edge_src);
   k_bin_plan<<<1, 1024, 0, s>>>(totals, n_bins, reduce_grid, bin_start, block_start, block_first_bin, rec_max_bits);
   return hipGetLastError();
 }

@@ -4,10 +4,13 @@
 //                 float4 grid-stride streams over 1 GiB (no index arithmetic beyond the stride),
 //                 each at several grid sizes; the best is the stream ceiling
 //   copy_l2       float4 copy within a 2 MiB buffer, repeated inside the kernel (L2-resident)
-//   encode_*      the forward pass's gathers alone: the 16-level hash grid of the 256^3 workload
+//   encode_*      the encoder's memory work alone: the 16-level hash grid of the 256^3 workload
 //                 (T = 2^19, resolutions 16 .. 2048) at the stratified samples of 2048 cone-beam rays
-//                 of one view x 192 samples, with the forward's lane layout (32 points per wave,
-//                 lane half h gathers half of the levels), FP32 x 2 or FP16 x 2 entries
+//                 of one view x 192 samples, gathered level-major with the training step's placement
+//                 (one lane per point, each XCD on one level at a time) and the encoding stored,
+//                 FP32 x 2 or FP16 x 2 entries; encode_lanes_* the same gathers in the layout of a
+//                 forward kernel that gathers every level itself (two lanes per point, lane half h
+//                 taking half of the levels, all levels on every XCD), for comparison
 //   gather_*      random 8-corner cells (four x-adjacent entry pairs, as at a hash-grid level) of
 //                 8-B (FP32 x 2) or 4-B (FP16 x 2) entries in tables of 0.94, 48.8 and 169 MB
 //   atomic_*      two global f32 atomic adds per corner, spread over a 48.8 MB table or contended
@@ -88,8 +91,43 @@ __global__ void k_ub_rays(Geo g, double ca, double sa, int n_rays, int n_pix, in
   rays[r] = rr;
 }
 
-// The forward pass's gathers alone: same chunking (4 waves x 32 points), same lane halves, same
-// level pairing; the 2 x L/2 interpolated features of a lane are summed into one output per point.
+// The encoder's gathers and encoding store alone, placed as in the training step: block b runs on
+// XCD b mod 8 and takes level b mod 8 + 8 * phase (phase = (b / 8) / G) for the points of group w =
+// (b / 8) mod G (chunks w, w + G, ... of kPtsPerBlock points, two at a time), one lane per point.
+template <bool HALF>
+__global__ void __launch_bounds__(kEncThreads) k_encode_lvl(const LevelTab T, const void* __restrict__ table,
+                                                            const RayRec* __restrict__ rays, Geo g, int N,
+                                                            int64_t n_points, int G, float2* __restrict__ out) {
+  const int s = (int)(blockIdx.x >> 3), ph = s / G, w = s - ph * G;
+  const int l = (int)(blockIdx.x & 7u) + 8 * ph;
+  if (l >= T.L) return;
+  const int64_t n_chunks = (n_points + kPtsPerBlock - 1) / kPtsPerBlock;
+  constexpr int kAtOnce = kEncThreads / kPtsPerBlock;
+  for (int64_t c = w + (int64_t)(threadIdx.x / kPtsPerBlock) * G; c < n_chunks; c += (int64_t)kAtOnce * G) {
+    const int64_t p = c * kPtsPerBlock + (threadIdx.x % kPtsPerBlock);
+    if (p >= n_points) continue;
+    const int64_t ray = p / N;
+    const RayRec rr = rays[ray];
+    float x[3] = {0.0f, 0.0f, 0.0f};
+    if (rr.hit) sample_pos(g, rr, (int)(p - ray * N), u24f(mix32((unsigned)p)), x);
+    uint32_t idx[8];
+    float w8[8];
+    level_corners(T.res[l], T.off[l], T.stride[l], T.mask, x, idx, w8);
+    float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      float2 v;
+      if constexpr (HALF) v = __half22float2(reinterpret_cast<const __half2*>(table)[idx[k]]);
+      else v = reinterpret_cast<const float2*>(table)[idx[k]];
+      s0 += w8[k] * v.x;
+      s1 += w8[k] * v.y;
+    }
+    out[(int64_t)l * n_points + p] = make_float2(s0, s1);
+  }
+}
+
+// The same gathers in a forward kernel's own layout: 4 waves x 32 points per chunk, lane half h
+// gathering levels 4j + 2h + q, every level on every XCD; one summed output per point.
 template <int L, bool HALF>
 __global__ void __launch_bounds__(kBlock, 2) k_encode_only(const LevelTab T, const void* __restrict__ table,
                                                            const RayRec* __restrict__ rays, Geo g, int N,
@@ -307,29 +345,38 @@ void encode_ceiling(Timer& tm) {
   void* table;
   const int64_t P = (int64_t)R * N;
   UB_CHECK(hipMalloc(&rays, sizeof(RayRec) * R));
-  UB_CHECK(hipMalloc(&out, sizeof(float) * P));
+  UB_CHECK(hipMalloc(&out, sizeof(float2) * P * L));
   UB_CHECK(hipMalloc(&table, n_entries * 8));
   UB_CHECK(hipMemset(table, 0, n_entries * 8));
   k_ub_rays<<<(R + 255) / 256, 256>>>(g, std::cos(th), std::sin(th), R, n_det * n_det, N, rays);
   int dev = 0, n_cu = 0;
   UB_CHECK(hipGetDevice(&dev));
   UB_CHECK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int grid = n_cu * n_cu_blocks_per;
+  const int grid = n_cu * n_cu_blocks_per;   // the backward grid of the step: point groups
   const double gathers = (double)P * L * 8;
-  for (int half = 0; half < 2; ++half) {
-    auto launch = [&]() {
-      if (half) k_encode_only<L, true><<<grid, kBlock>>>(lt, table, rays, g, N, P, out);
-      else k_encode_only<L, false><<<grid, kBlock>>>(lt, table, rays, g, N, P, out);
-    };
-    launch();
-    tm.start();
-    for (int r = 0; r < 4 * kReps; ++r) launch();
-    const float ms = tm.stop_ms() / (4 * kReps);
-    const char* nm = half ? "encode_fp16" : "encode_fp32";
-    std::printf("%s 256^3 workload (%lld points x 16 levels x 8 corners, table %.1f MB): %.1f us per step, "
-                "%.1f G gathers/s\n", nm, (long long)P, n_entries * (half ? 4.0 : 8.0) / 1e6, ms * 1e3,
-                gathers / (ms * 1e-3) / 1e9);
-    std::printf("ceiling %s %.2f us\n", nm, ms * 1e3);
+  for (int lanes = 0; lanes < 2; ++lanes) {
+    for (int half = 0; half < 2; ++half) {
+      auto launch = [&]() {
+        if (lanes) {
+          if (half) k_encode_only<L, true><<<grid, kBlock>>>(lt, table, rays, g, N, P, out);
+          else k_encode_only<L, false><<<grid, kBlock>>>(lt, table, rays, g, N, P, out);
+        } else {
+          const unsigned blocks = 8u * ((L + 7) / 8) * (unsigned)grid;
+          float2* o2 = reinterpret_cast<float2*>(out);
+          if (half) k_encode_lvl<true><<<blocks, kEncThreads>>>(lt, table, rays, g, N, P, grid, o2);
+          else k_encode_lvl<false><<<blocks, kEncThreads>>>(lt, table, rays, g, N, P, grid, o2);
+        }
+      };
+      launch();
+      tm.start();
+      for (int r = 0; r < 4 * kReps; ++r) launch();
+      const float ms = tm.stop_ms() / (4 * kReps);
+      const char* nm = lanes ? (half ? "encode_lanes_fp16" : "encode_lanes_fp32") : (half ? "encode_fp16" : "encode_fp32");
+      std::printf("%s 256^3 workload (%lld points x 16 levels x 8 corners, table %.1f MB): %.1f us per step, "
+                  "%.1f G gathers/s\n", nm, (long long)P, n_entries * (half ? 4.0 : 8.0) / 1e6, ms * 1e3,
+                  gathers / (ms * 1e-3) / 1e9);
+      if (!lanes) std::printf("ceiling %s %.2f us\n", nm, ms * 1e3);
+    }
   }
   UB_CHECK(hipFree(rays));
   UB_CHECK(hipFree(out));

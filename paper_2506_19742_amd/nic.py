@@ -58,7 +58,7 @@ EXPORTS = ["nic_describe", "nic_workspace_size", "nic_create", "nic_destroy", "n
            "nic_set_projections", "nic_tensors", "nic_sync_params", "nic_init_params", "nic_step",
            "nic_train", "nic_view_for_step", "nic_draw_rays", "nic_forward", "nic_backward",
            "nic_adam", "nic_zero_grad", "nic_query", "nic_render_volume", "nic_encode",
-           "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step",
+           "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step", "nic_set_level_major_encoder",
            "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr",
            "nic_save_state", "nic_load_state", "nic_field_from_features", "nic_ssim",
            "nic_set_channel_mask", "nic_channel_spectrum", "nic_sync", "nic_psnr_noalloc"]
@@ -97,6 +97,7 @@ def lib():
             "nic_encode": ([vp, vp, C.c_int64, vp, vp], C.c_int32),
             "nic_get_step": ([vp], C.c_int64),
             "nic_set_timing": ([vp, C.c_int32], C.c_int32),
+            "nic_set_level_major_encoder": ([vp, C.c_int32], C.c_int32),
             "nic_kernel_times": ([vp, P(C.c_double), P(C.c_int64), P(C.c_int32)], C.c_int32),
             "nic_voxel_step": ([vp, vp, C.c_int32, vp], C.c_int32),
             "nic_voxel_train": ([vp, C.c_int32, C.c_int32, P(C.c_float)], C.c_int32),
@@ -363,7 +364,12 @@ class Model:
     def get_step(self) -> int:
         return int(lib().nic_get_step(self.h))
 
-    KERNEL_KINDS = ("rays", "forward", "backward", "reduce", "adam", "bin_scan", "bin_reduce")
+    KERNEL_KINDS = ("rays", "forward", "backward", "encode", "adam", "bin_scan", "bin_reduce")
+
+    def set_level_major_encoder(self, enable: bool):
+        """Ray training steps encode in the level-major kernel (True, the default) or inside the
+        forward kernel (False); the results are bitwise identical."""
+        _check(lib().nic_set_level_major_encoder(self.h, 1 if enable else 0))
 
     def set_timing(self, enable: bool):
         _check(lib().nic_set_timing(self.h, 1 if enable else 0))

@@ -31,7 +31,8 @@ def test_algorithmic_bytes_ct256(precision):
     # 16 levels x 8 corners x 2 features, 4-byte gradients; gathers of 4 (FP32) or 2 (FP16) bytes
     assert ab["per_point"] == 16 * 8 * 2 * 4 == 1024
     assert ab["backward"] == 393216 * 1024 == 402653184
-    assert ab["forward"] == 393216 * 16 * 8 * 2 * (2 if precision else 4)
+    assert ab["encode"] == 393216 * 16 * 8 * 2 * (2 if precision else 4)
+    assert ab["forward"] == 393216 * 16 * 2 * 4          # the stored encoding, read back
     # the fused bin reduction also reads and writes each table parameter and its two moments
     n_table = lay["n_table"]
     assert ab["bin_reduce"] == 402653184 + n_table * (24 + (2 if precision else 0))
@@ -78,7 +79,8 @@ def test_pmc_summary_scales_counters_by_the_copy(tmp_path, capsys):
                                         (2, "k_fwd<16, 32, 4, 0>", "FETCH_SIZE", 3000.0),
                                         (3, "k_bin_reduce<true>", "FETCH_SIZE", 100.0),
                                         (4, "k_bin_combine", "FETCH_SIZE", 50.0),
-                                        (5, "k_rays", "FETCH_SIZE", 7.0)])
+                                        (5, "k_rays", "FETCH_SIZE", 7.0),
+                                        (6, "k_enc<16, 0>", "FETCH_SIZE", 400.0)])
     _write_counter_csv(tmp_path / "w", [(1, "void nic::k_fwd<16, 32, 4, 0>(nic::FwdArgs)", "WRITE_SIZE", 10.0),
                                         (3, "k_bin_reduce<true>", "WRITE_SIZE", 20.0)])
     out = tmp_path / "traffic.json"
@@ -93,12 +95,14 @@ def test_pmc_summary_scales_counters_by_the_copy(tmp_path, capsys):
     assert k["bin_reduce"]["read"] == pytest.approx(150.0 * 1024 * 2)
     assert k["bin_reduce"]["bytes_per_launch"] == pytest.approx(150.0 * 1024 * 2 + 20.0 * 1024)
     assert "rays" not in k
+    assert k["encode"]["read"] == pytest.approx(400.0 * 1024 * 2)
     assert "| `k_fwd<16, 32, 4, 0>` |" in capsys.readouterr().out
 
 
 def test_achievable_fractions():
-    kt = {"forward": (2.0, 10), "backward": (3.0, 10), "bin_reduce": (2.0, 10), "adam": (0.0, 0)}
-    ab = {"forward": 4e8, "backward": 4e8, "bin_reduce": 7e8}
+    kt = {"encode": (2.0, 10), "forward": (0.5, 10), "backward": (3.0, 10), "bin_reduce": (2.0, 10),
+          "adam": (0.0, 0)}
+    ab = {"encode": 4e8, "forward": 5e7, "backward": 4e8, "bin_reduce": 7e8}
     ceil = {"encode_fp32": {"value": 100.0, "unit": "us"}, "stream_copy": {"value": 5000.0, "unit": "GB/s"}}
     a = bench.achievable(kt, ab, ceil, {"backward": None, "bin_reduce": None}, 0, "ct256")
     assert a["encode"]["frac"] == pytest.approx(100.0 / 200.0)
