@@ -299,14 +299,21 @@ nic_status nic_ssim(nic_model* m, const float* gt_dev, const float* pred_dev, co
 int64_t nic_get_step(const nic_model* m);
 
 /* Encoder placement of the ray training steps (nic_train, nic_step, nic_backward) on a model with
- * one table.  enable != 0 (the default): a level-major encoder kernel computes the hash encoding
+ * one table.  NIC_ENCODER_LEVEL_MAJOR: a level-major encoder kernel computes the hash encoding
  * (Sec. 2.2) and the gradient-record counts, with each XCD of the chip working on one level of the
  * grid at a time so that the level's table stays in that XCD's L2, and the forward kernel reads
- * the stored encoding.  enable == 0: the forward kernel gathers all levels itself.  Both give
- * bitwise identical results (same arithmetic in the same order); the switch is for measurement and
- * testing.  Every other pass (queries, rendering, pre-training) always uses the second form.
- * Errors: NIC_EINVAL for a NULL model. */
-nic_status nic_set_level_major_encoder(nic_model* m, int32_t enable);
+ * the stored encoding.  NIC_ENCODER_IN_FORWARD: the forward kernel gathers all levels itself.
+ * NIC_ENCODER_AUTO (the default): level-major when the whole table (8 B per entry, 4 B in the
+ * precision form) exceeds the device's L2 size and no level's table exceeds twice it.  All give
+ * bitwise identical results (same arithmetic in the same order).  Every other pass (queries,
+ * rendering, pre-training) always encodes inside its own kernel.  nic_encoder_level_major returns 1
+ * when the training steps of m currently use the level-major encoder (0 for a NULL model).
+ * Errors: NIC_EINVAL for a NULL model or another placement value. */
+#define NIC_ENCODER_AUTO 0
+#define NIC_ENCODER_LEVEL_MAJOR 1
+#define NIC_ENCODER_IN_FORWARD 2
+nic_status nic_set_encoder_placement(nic_model* m, int32_t placement);
+int32_t nic_encoder_level_major(const nic_model* m);
 
 /* Kernel timing for benchmarks: with enable != 0, every kernel of the training path is bracketed
  * by a pair of HIP events on the model's stream.  nic_kernel_times synchronises the stream and

@@ -291,7 +291,8 @@ struct nic_model {
   std::vector<int32_t> epoch_order;
   // kernel timing (benchmarks)
   bool timing = false;
-  bool level_major = true;    // ray training steps on one table encode in k_enc
+  int32_t enc_placement = NIC_ENCODER_AUTO;   // where ray training steps on one table encode
+  bool level_major_pays = false;              // the auto rule for this model on this device
   int64_t rec_cap = 0;        // capacity of recs (records)
   uint32_t* edge = nullptr;
   int32_t *ebeg = nullptr, *esrc = nullptr;
@@ -418,7 +419,9 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
   const size_t bin_lds = (size_t)pl.n_bins * 4;
   // Rays on one table: the level-major encoder k_enc computes the encoding and the record counts,
   // and k_fwd only reads the encoding.  Otherwise k_fwd gathers and counts itself.
-  const bool lvl = m->level_major && a.mode == kModeRays && pl.n_tables == 1 && !a.feats && pl.ks.enc;
+  const bool want = m->enc_placement == NIC_ENCODER_LEVEL_MAJOR ||
+                    (m->enc_placement == NIC_ENCODER_AUTO && m->level_major_pays);
+  const bool lvl = want && a.mode == kModeRays && pl.n_tables == 1 && !a.feats && pl.ks.enc;
   a.enc_out = m->enc;
   a.wave_sum = m->wsum;
   a.bin_counts = m->counts;
@@ -688,7 +691,8 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
     e = hipFuncSetAttribute(bin_reduce_kernel(true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bin_reduce_lds());
   if (e == hipSuccess)
     e = hipFuncSetAttribute(bin_reduce_kernel(false), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bin_reduce_lds());
-  int per_cu = 0, per_cu_red = 0;
+  int per_cu = 0, per_cu_red = 0, l2 = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&l2, hipDeviceAttributeL2CacheSize, dev);
   if (e == hipSuccess)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.ks.bwd, kBlock, p.ks.bwd_lds + bin_lds);
   if (e == hipSuccess)
@@ -698,6 +702,18 @@ nic_status nic_create(const nic_config* cfg, const nic_geometry* geom, void* hip
     return fail(NIC_EHIP, "device query: %s", hipGetErrorString(e));
   }
   m->bwd_grid = std::max(1, std::min(kMaxBwdBlocks, m->n_cu * std::max(1, per_cu)));
+  // The level-major encoder pays when the whole table overflows an XCD's L2 but one level's table
+  // fits in about twice that (measured: 2 and 4 MB levels gain 1.3-1.7x on the encode, 8 MB ones
+  // 1.1x, 16 MB ones lose; a table that fits in L2 as a whole loses the extra pass).
+  {
+    const int64_t eb = cfg->precision ? 4 : 8, l2b = l2 > 0 ? l2 : (4 << 20);
+    int64_t lvl_max = 0;
+    for (int l = 0; l < cfg->n_levels; ++l) {
+      const int64_t st = p.lt.stride[l];
+      lvl_max = std::max<int64_t>(lvl_max, (st ? st * st * st : (int64_t)p.lt.mask + 1) * eb);
+    }
+    m->level_major_pays = p.n_entries * eb > l2b && lvl_max <= 2 * l2b;
+  }
   m->reduce_grid = std::max(1, std::min(kMaxReduceBlocks, m->n_cu * std::max(1, per_cu_red)));
 
   char* ws = (char*)workspace;
@@ -759,10 +775,19 @@ void nic_destroy(nic_model* m) {
   delete m;
 }
 
-nic_status nic_set_level_major_encoder(nic_model* m, int32_t enable) {
+nic_status nic_set_encoder_placement(nic_model* m, int32_t placement) {
   if (!model_ok(m)) return fail(NIC_EINVAL, "model is NULL");
-  m->level_major = enable != 0;
+  if (placement != NIC_ENCODER_AUTO && placement != NIC_ENCODER_LEVEL_MAJOR && placement != NIC_ENCODER_IN_FORWARD)
+    return fail(NIC_EINVAL, "placement must be NIC_ENCODER_AUTO, _LEVEL_MAJOR or _IN_FORWARD");
+  m->enc_placement = placement;
   return NIC_OK;
+}
+
+int32_t nic_encoder_level_major(const nic_model* m) {
+  if (!m) return 0;
+  const bool want = m->enc_placement == NIC_ENCODER_LEVEL_MAJOR ||
+                    (m->enc_placement == NIC_ENCODER_AUTO && m->level_major_pays);
+  return want && m->plan.n_tables == 1 ? 1 : 0;
 }
 
 nic_status nic_set_timing(nic_model* m, int32_t enable) {

@@ -58,8 +58,8 @@ EXPORTS = ["nic_describe", "nic_workspace_size", "nic_create", "nic_destroy", "n
            "nic_set_projections", "nic_tensors", "nic_sync_params", "nic_init_params", "nic_step",
            "nic_train", "nic_view_for_step", "nic_draw_rays", "nic_forward", "nic_backward",
            "nic_adam", "nic_zero_grad", "nic_query", "nic_render_volume", "nic_encode",
-           "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step", "nic_set_level_major_encoder",
-           "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr",
+           "nic_get_step", "nic_set_timing", "nic_kernel_times", "nic_voxel_step",
+           "nic_set_encoder_placement", "nic_encoder_level_major", "nic_voxel_train", "nic_set_volumes", "nic_export_mlp", "nic_import_mlp", "nic_psnr",
            "nic_save_state", "nic_load_state", "nic_field_from_features", "nic_ssim",
            "nic_set_channel_mask", "nic_channel_spectrum", "nic_sync", "nic_psnr_noalloc"]
 
@@ -97,7 +97,8 @@ def lib():
             "nic_encode": ([vp, vp, C.c_int64, vp, vp], C.c_int32),
             "nic_get_step": ([vp], C.c_int64),
             "nic_set_timing": ([vp, C.c_int32], C.c_int32),
-            "nic_set_level_major_encoder": ([vp, C.c_int32], C.c_int32),
+            "nic_set_encoder_placement": ([vp, C.c_int32], C.c_int32),
+            "nic_encoder_level_major": ([vp], C.c_int32),
             "nic_kernel_times": ([vp, P(C.c_double), P(C.c_int64), P(C.c_int32)], C.c_int32),
             "nic_voxel_step": ([vp, vp, C.c_int32, vp], C.c_int32),
             "nic_voxel_train": ([vp, C.c_int32, C.c_int32, P(C.c_float)], C.c_int32),
@@ -366,10 +367,17 @@ class Model:
 
     KERNEL_KINDS = ("rays", "forward", "backward", "encode", "adam", "bin_scan", "bin_reduce")
 
-    def set_level_major_encoder(self, enable: bool):
-        """Ray training steps encode in the level-major kernel (True, the default) or inside the
-        forward kernel (False); the results are bitwise identical."""
-        _check(lib().nic_set_level_major_encoder(self.h, 1 if enable else 0))
+    ENCODER_PLACEMENTS = {"auto": 0, "level_major": 1, "in_forward": 2}
+
+    def set_encoder_placement(self, placement: str):
+        """Where ray training steps encode: "level_major" (a kernel of its own, one level per XCD at
+        a time), "in_forward" (inside the forward kernel) or "auto" (the default: level-major when
+        the table overflows an XCD's L2 and a level's table fits in about twice it).  The results
+        are bitwise identical."""
+        _check(lib().nic_set_encoder_placement(self.h, self.ENCODER_PLACEMENTS[placement]))
+
+    def encoder_level_major(self) -> bool:
+        return bool(lib().nic_encoder_level_major(self.h))
 
     def set_timing(self, enable: bool):
         _check(lib().nic_set_timing(self.h, 1 if enable else 0))

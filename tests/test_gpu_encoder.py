@@ -6,7 +6,10 @@ table-gradient records there; the forward kernel then reads the stored encoding.
 arithmetic in the same order as the forward kernel gathering every level itself, so the two
 placements must give bitwise identical training: the losses of every step and, after the steps,
 the parameters, gradient, both Adam moments and the FP16 table copy.  A record counted for the
-wrong bin or block would move records between bins or leave slots stale, and show here.
+wrong bin or block would move records between bins or leave slots stale, and show here.  Both
+placements are forced here; the default picks the level-major one where it pays (the table larger
+than an XCD's L2, each level's table at most twice it), which the last test checks for the three
+workloads.
 
 Cases: the three workloads at both precisions (8 levels: a single phase of levels; 16: two), a
 small batch whose last chunk is partial (97 rays x 32 samples over 25 backward blocks), a channel
@@ -26,9 +29,10 @@ pytestmark = pytest.mark.gpu
 def _train_both(cfg, g, proj, steps, mask=None):
     """Losses of `steps` training steps, after checking both placements agree bit for bit."""
     runs = []
-    for level_major in (True, False):
+    for placement in ("level_major", "in_forward"):
         m = nic.Model(cfg, g)
-        m.set_level_major_encoder(level_major)
+        m.set_encoder_placement(placement)
+        assert m.encoder_level_major() == (placement == "level_major")
         m.set_projections(proj)
         if mask is not None:
             m.set_channel_mask(mask)
@@ -45,7 +49,7 @@ def _train_both(cfg, g, proj, steps, mask=None):
 
 
 @pytest.mark.parametrize("workload,precision", [("tiny64", 0), ("tiny64", 1), ("ct256", 0), ("ct256", 1),
-                                                ("ct512", 1)])
+                                                ("ct512", 0), ("ct512", 1)])
 def test_level_major_encoder_is_bitwise_identical(workload, precision):
     print(f"[case] encoder placement {workload} precision {precision}", flush=True)
     w = synth.WORKLOADS[workload]
@@ -91,3 +95,24 @@ def test_level_major_encoder_rays_missing_the_box():
     ph = synth.make_phantom(3, 5)
     A = synth.project(ph, g).astype(np.float32)
     _train_both(nic.config_for(w, seed=54, rays_per_step=256), g, torch.tensor(A, device="cuda"), 3)
+
+
+def test_default_placement_follows_the_l2_size():
+    """tiny64 (0.94 MB table: fits in L2) and ct512 FP32 (16 MB per level) encode in the forward
+    kernel; ct256 (4 MB / 2 MB per level) and ct512 FP16 (8 MB per level) level-major."""
+    l2 = torch.cuda.get_device_properties(0).L2_cache_size
+    print(f"[case] default encoder placement, L2 {l2} bytes", flush=True)
+    assert l2 == 4 << 20            # one XCD's L2 on this GPU: the rule's unit
+    want = {("tiny64", 0): False, ("tiny64", 1): False, ("ct256", 0): True, ("ct256", 1): True,
+            ("ct512", 0): False, ("ct512", 1): True}
+    for (wl, prec), lm in want.items():
+        w = synth.WORKLOADS[wl]
+        m = nic.Model(nic.config_for(w, seed=55, precision=prec), synth.cone_geometry(w.n_det, 4))
+        assert m.encoder_level_major() == lm, (wl, prec)
+        m.set_encoder_placement("in_forward")
+        assert not m.encoder_level_major()
+        m.set_encoder_placement("auto")
+        assert m.encoder_level_major() == lm
+        assert nic.lib().nic_set_encoder_placement(m.h, 3) == nic.NIC_EINVAL
+        assert m.encoder_level_major() == lm
+        m.close()
