@@ -655,9 +655,11 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_fwd(const FwdArgs a
 // k_bwd read it (register 4(l/4) + 2(l%2) + f of lane half (l/2)%2, as encode_half leaves it) and
 // counts the records block w of k_bwd will write for level l, per bin.
 // Placement: workgroups go to the 8 XCDs of the chip in turn (block b to XCD b mod 8), so with
-// b = 8 (phase * G + w) + x and l = x + 8 phase each XCD works on one level at a time, and that
-// level's table (4 MB at FP32, 2 MB at FP16 for T = 2^19) stays in the XCD's own L2 instead of
-// the whole table streaming through every L2.
+// b = 8 (phase * G + w) + x each XCD works on one level at a time, and that level's table (4 MB at
+// FP32, 2 MB at FP16 for T = 2^19) stays in the XCD's own L2 instead of the whole table streaming
+// through every L2.  The phases run over the levels in serpentine order (phase 0: l = x, phase 1:
+// l = 15 - x, ...): a level costs more the finer it is, so each XCD pairs a coarse level with a
+// fine one and the XCDs finish together.
 // One lane per point; lanes 32k .. 32k + 31 of a wave hold the 32 points of one backward wave, so
 // the runs (run_flags) and the records counted are exactly those of scatter_half.  Level l is
 // skipped (zero encoding, no records) exactly when scatter_half and encode_half skip its pair.
@@ -673,7 +675,8 @@ __global__ void __launch_bounds__(kEncThreads) k_enc(const FwdArgs a) {
   const int G = a.enc_grid;
   const int s = (int)(blockIdx.x >> 3);
   const int ph = s / G, w = s - ph * G;
-  const int l = (int)(blockIdx.x & 7u) + 8 * ph;
+  const int x = (int)(blockIdx.x & 7u);
+  const int l = 8 * ph + ((ph & 1) ? 7 - x : x);
   if (l >= L) return;                                   // block-uniform, before any barrier
   const LevelTab& T = a.lt;
   const int32_t N = T.res[l];

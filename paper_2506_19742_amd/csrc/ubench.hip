@@ -92,14 +92,16 @@ __global__ void k_ub_rays(Geo g, double ca, double sa, int n_rays, int n_pix, in
 }
 
 // The encoder's gathers and encoding store alone, placed as in the training step: block b runs on
-// XCD b mod 8 and takes level b mod 8 + 8 * phase (phase = (b / 8) / G) for the points of group w =
-// (b / 8) mod G (chunks w, w + G, ... of kPtsPerBlock points, two at a time), one lane per point.
+// XCD x = b mod 8 and takes level 8 * phase + (x, or 7 - x in odd phases) (phase = (b / 8) / G) for
+// the points of group w = (b / 8) mod G (chunks w, w + G, ... of kPtsPerBlock points, two at a
+// time), one lane per point.
 template <bool HALF>
 __global__ void __launch_bounds__(kEncThreads) k_encode_lvl(const LevelTab T, const void* __restrict__ table,
                                                             const RayRec* __restrict__ rays, Geo g, int N,
                                                             int64_t n_points, int G, float2* __restrict__ out) {
   const int s = (int)(blockIdx.x >> 3), ph = s / G, w = s - ph * G;
-  const int l = (int)(blockIdx.x & 7u) + 8 * ph;
+  const int x = (int)(blockIdx.x & 7u);
+  const int l = 8 * ph + ((ph & 1) ? 7 - x : x);
   if (l >= T.L) return;
   const int64_t n_chunks = (n_points + kPtsPerBlock - 1) / kPtsPerBlock;
   constexpr int kAtOnce = kEncThreads / kPtsPerBlock;
