@@ -11,7 +11,8 @@ placements are forced here; the default picks the level-major one where it pays 
 than an XCD's L2, each level's table at most twice it), which the last test checks for the three
 workloads.
 
-Cases: the three workloads at both precisions (8 levels: a single phase of levels; 16: two), a
+Cases: the three workloads at both precisions (8 levels: a single phase of levels; 16: two), small
+tables whose gradient bins each hold eight levels, the 64-wide network, a
 small batch whose last chunk is partial (97 rays x 32 samples over 25 backward blocks), a channel
 mask that turns off a level pair and one level of another pair (the second level of that pair is
 still gathered and scattered), and a detector shifted so that some rays miss the volume.
@@ -116,3 +117,22 @@ def test_default_placement_follows_the_l2_size():
         assert nic.lib().nic_set_encoder_placement(m.h, 3) == nic.NIC_EINVAL
         assert m.encoder_level_major() == lm
         m.close()
+
+
+@pytest.mark.parametrize("workload,log2_table,width", [("tiny64", 10, 32), ("ct256", 10, 32), ("tiny64", 14, 64)])
+def test_level_major_encoder_shared_bins_and_wide_mlp(workload, log2_table, width):
+    """T = 2^10: every level is a hashed table of 1024 entries, so one 8192-entry gradient bin holds
+    the entries of eight levels (tiny64: all 8 levels in a single bin; ct256: 16 levels in two bins)
+    and each such bin's count is the sum of eight levels' edge rows.  Width 64: the 8-level, 64-wide
+    kernel set."""
+    print(f"[case] encoder placement {workload} T=2^{log2_table} W={width}", flush=True)
+    w = synth.WORKLOADS[workload]
+    _, g, A = synth.scan(w)
+    over = dict(seed=56, log2_table=log2_table, mlp_width=width)
+    if width == 64:
+        over["mlp_depth"] = 4
+    cfg = nic.config_for(w, **over)
+    lay = nic.nic_describe(cfg)
+    if log2_table == 10:
+        assert lay["n_bins"] == (1 if workload == "tiny64" else 2)
+    _train_both(cfg, g, torch.tensor(A, device="cuda"), 3)
