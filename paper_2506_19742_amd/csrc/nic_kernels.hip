@@ -389,10 +389,10 @@ __device__ __forceinline__ void tile_put_bf16(__bf16* tile, const float* v, int 
   }
 }
 
-// BF16 form of tile_outer: K = 32 points in two steps of 16.
-__device__ __forceinline__ f32x16 tile_outer_bf16(const __bf16* tG, const __bf16* tH, int lane) {
+// BF16 form of tile_outer: K = 32 points in two steps of 16, added to d.
+__device__ __forceinline__ f32x16 tile_outer_bf16(const __bf16* tG, const __bf16* tH, int lane,
+                                                  f32x16 d = f32x16{}) {
   const int m = lane & 31, h = lane >> 5;
-  f32x16 d = f32x16{};
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const bf16x8 a = *reinterpret_cast<const bf16x8*>(tG + m * kTile16 + 16 * s + 8 * h);
@@ -423,11 +423,10 @@ __device__ __forceinline__ float tile_rowsum(const float* tile, int lane) {
   return s + xor32(s);
 }
 
-// G^T H over the wave's 32 points for tiles tG = G rows [32mb, 32mb+32), tH = H rows [32nb, ..):
-// register r of lane (m, h) = entry (32mb + chan(r, h), 32nb + m).
-__device__ __forceinline__ f32x16 tile_outer(const float* tG, const float* tH, int lane) {
+// G^T H over the 32 points of a tile pair, tG = G rows [32mb, 32mb+32), tH = H rows [32nb, ..),
+// added to d: register r of lane (m, h) = entry (32mb + chan(r, h), 32nb + m).
+__device__ __forceinline__ f32x16 tile_outer(const float* tG, const float* tH, int lane, f32x16 d = f32x16{}) {
   const int m = lane & 31, h = lane >> 5;
-  f32x16 d = f32x16{};
 #pragma unroll
   for (int s = 0; s < 16; ++s) d = mfma32(tG[m * kTile + 16 * h + s], tH[m * kTile + 16 * h + s], d);
   return d;
@@ -746,21 +745,37 @@ __global__ void __launch_bounds__(kEncThreads) k_enc(const FwdArgs a) {
 // ---------------------------------------------------------------------------------------------
 // Backward kernel (persistent over 128-point chunks)
 // ---------------------------------------------------------------------------------------------
+// Floats of k_bwd's LDS after the staged parameters and before the bin cursors: W = 32 the dense
+// accumulator and two tiles per wave; W = 64 four tile slots per wave, which the dense gradient
+// reuses at the end.
+template <int W>
+__host__ __device__ constexpr int bwd_tiles_lds(int nd_pad) {
+  return W == 64 ? (nd_pad > 4 * kWavesPerBlock * 32 * kTile ? nd_pad : 4 * kWavesPerBlock * 32 * kTile)
+                 : nd_pad + kWavesPerBlock * 2 * 32 * kTile;
+}
+
 template <int L, int W, int D, int P>
 __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a, const BwdArgs b) {
   constexpr int C = 2 * L, RC = C / 2, RW = W / 2;
   using Ly = Lay<C, W, D, P>;
+  // 64 wide (one block per CU): every wave owns one 32x32 weight-gradient tile of each layer and
+  // sums it in registers over all 128 points of every chunk, reading the other waves' blocks from
+  // four tile slots per wave; the block's dense gradient is assembled once, at the end.  32 wide:
+  // each wave's tiles over its own 32 points, combined across the waves chunk by chunk.
+  constexpr bool kOwn = W == 64;
+  constexpr int kSlot = 32 * kTile, nd_pad = (Ly::g_n + 3) & ~3;
   extern __shared__ float smem[];
   float* sp = smem;
-  float* acc = smem + Ly::s_n;
-  const int nd_pad = (Ly::g_n + 3) & ~3;
+  float* acc = smem + Ly::s_n;                  // kOwn: assembled at the end, over the slots
+  float* const slots = smem + Ly::s_n;          // kOwn: slots [wave][4][32][kTile]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
-  float* tG = acc + nd_pad + wv * (2 * 32 * kTile);
-  float* tH = tG + 32 * kTile;
-  uint32_t* cursor = reinterpret_cast<uint32_t*>(acc + nd_pad + kWavesPerBlock * 2 * 32 * kTile);
+  float* tG = kOwn ? slots + (4 * wv + 3) * kSlot : acc + nd_pad + wv * (2 * kSlot);
+  float* tH = tG + kSlot;                       // (not used when kOwn)
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(smem + Ly::s_n + bwd_tiles_lds<W>(nd_pad));
 
   stage_params<C, W, D, P>(a.dense, sp);
-  for (int e2 = threadIdx.x; e2 < nd_pad; e2 += blockDim.x) acc[e2] = 0.0f;
+  if constexpr (!kOwn)
+    for (int e2 = threadIdx.x; e2 < nd_pad; e2 += blockDim.x) acc[e2] = 0.0f;
   for (int b2 = threadIdx.x; b2 < a.n_bins; b2 += blockDim.x)
     cursor[b2] = b.bin_start[b2] + b.bin_offsets[(size_t)b2 * gridDim.x + blockIdx.x];
   __syncthreads();
@@ -769,6 +784,15 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
   const int64_t n_chunks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
   uint32_t vbits = 0u;   // largest |record| as a bit pattern: NaN and inf order above every finite value
   bool bad = false;      // a residual, upstream gradient or dense partial that is not finite
+  // kOwn: the wave's weight-gradient tile of each layer, and its own points' bias, output-unit and
+  // LayerNorm row sums (row lane % 32), over the block's chunks
+  f32x16 ownW[D];
+  float ownB[D][2], ownWo[2] = {0.0f, 0.0f}, ownLg = 0.0f, ownLb = 0.0f, ownBo = 0.0f;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    ownW[k] = f32x16{};
+    ownB[k][0] = ownB[k][1] = 0.0f;
+  }
   for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
     const int64_t wave_id = chunk * kWavesPerBlock + wv;
     const int64_t p = wave_id * kPtsPerWave + n;
@@ -845,7 +869,9 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
     }
     const Combine cmb{acc + nd_pad, 2 * 32 * kTile, wv, lane};
     const float sdy = half_sum(h == 0 ? dy : 0.0f);
-    // row sums of the output weights' gradient, combined across waves with the LayerNorm's below
+    // row sums of the output weights' gradient (kOwn: in slot 3, which no other wave reads from
+    // the last layer's outer products of a chunk to the first one's of the next), combined across
+    // waves with the LayerNorm's below
     float rs[W / 32];
 #pragma unroll
     for (int mb = 0; mb < W / 32; ++mb) {
@@ -853,6 +879,11 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
       wave_lds_sync();
       rs[mb] = tile_rowsum(tG, lane);
       wave_lds_sync();
+    }
+    if constexpr (kOwn) {
+      ownWo[0] += rs[0];
+      ownWo[1] += rs[W / 32 - 1];
+      ownBo += sdy;
     }
 
     // Hidden layers, last to first.  Weight gradients: per 32x32 block, the FP32 tile of the layer's
@@ -868,6 +899,45 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
       for (int R = 0; R < RW; ++R) ga[R] = hb[k][R] > 0.0f ? g[R] : 0.0f;
       const int Kk = Ly::K(k);
       const float* hin = (k == 0) ? z : hb[k > 0 ? k - 1 : 0];
+      if constexpr (kOwn) {
+        // slots 0, 1: the wave's output-gradient blocks (FP32 for its bias row sums, then the
+        // BF16 operand tiles in the BF16 form); slots 2, 3: its input blocks (one at layer 0)
+        float* S = slots + 4 * wv * kSlot;
+        __syncthreads();                        // every wave is done with the slots' last contents
+        tile_put<RW>(S, ga, 0, lane);
+        tile_put<RW>(S + kSlot, ga, 1, lane);
+        wave_lds_sync();
+        ownB[k][0] += tile_rowsum(S, lane);
+        ownB[k][1] += tile_rowsum(S + kSlot, lane);
+        if constexpr (P == 1) {
+          wave_lds_sync();
+          tile_put_bf16<RW>(reinterpret_cast<__bf16*>(S), ga, 0, lane);
+          tile_put_bf16<RW>(reinterpret_cast<__bf16*>(S + kSlot), ga, 1, lane);
+        }
+        if (k == 0) {
+          if constexpr (P == 0) tile_put<RC>(S + 2 * kSlot, z, 0, lane);
+          else tile_put_bf16<RC>(reinterpret_cast<__bf16*>(S + 2 * kSlot), z, 0, lane);
+        } else {
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            if constexpr (P == 0) tile_put<RW>(S + (2 + nb) * kSlot, hin, nb, lane);
+            else tile_put_bf16<RW>(reinterpret_cast<__bf16*>(S + (2 + nb) * kSlot), hin, nb, lane);
+          }
+        }
+        __syncthreads();                        // every wave's blocks are in place
+        // the wave's tile: hidden layers (mb, nb) = (wv / 2, wv % 2) over the chunk's 128 points;
+        // layer 0 (one input block) rows mb = wv % 2 over the points of waves 2 (wv / 2) and + 1
+        const int mb = k == 0 ? (wv & 1) : (wv >> 1), nb = k == 0 ? 0 : (wv & 1);
+        const int q0 = k == 0 ? 2 * (wv >> 1) : 0;
+#pragma unroll
+        for (int q = 0; q < (k == 0 ? 2 : kWavesPerBlock); ++q) {
+          const float* Sq = slots + 4 * (q0 + q) * kSlot;
+          if constexpr (P == 0) ownW[k] = tile_outer(Sq + mb * kSlot, Sq + (2 + nb) * kSlot, lane, ownW[k]);
+          else
+            ownW[k] = tile_outer_bf16(reinterpret_cast<const __bf16*>(Sq + mb * kSlot),
+                                      reinterpret_cast<const __bf16*>(Sq + (2 + nb) * kSlot), lane, ownW[k]);
+        }
+      } else {
 #pragma unroll
       for (int mb = 0; mb < W / 32; ++mb) {
         tile_put<RW>(tG, ga, mb, lane);
@@ -895,6 +965,7 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
           c2.tile(acc, d, Ly::gW(k), Kk, mb, nb, brow, nb == 0 ? Ly::gb(k) : -1);
         }
       }
+      }
       if (k > 0) {
         float gp[RW];
         if constexpr (P == 0) layer_bwd_data<W, W>(sp + Ly::sW(k), ga, gp, lane);
@@ -920,12 +991,24 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
         sg += gg;
         sgx += gg * xh[r];
       }
-      tile_put<RC>(tG, t1, 0, lane);
-      tile_put<RC>(tH, t2, 0, lane);
-      wave_lds_sync();
-      const float rg = tile_rowsum(tG, lane), rb = tile_rowsum(tH, lane);
-      wave_lds_sync();
-      cmb.rows_merged(acc, rs[0], rs[W / 32 - 1], W == 64, Ly::g_wo, rg, rb, Ly::g_lng, Ly::g_lnb, C, sdy, Ly::g_bo);
+      if constexpr (kOwn) {   // slot 3 only (the other slots may still be read by layer 0's tiles)
+        tile_put<RC>(tG, t1, 0, lane);
+        wave_lds_sync();
+        ownLg += tile_rowsum(tG, lane);
+        wave_lds_sync();
+        tile_put<RC>(tG, t2, 0, lane);
+        wave_lds_sync();
+        ownLb += tile_rowsum(tG, lane);
+        wave_lds_sync();
+      } else {
+        tile_put<RC>(tG, t1, 0, lane);
+        tile_put<RC>(tH, t2, 0, lane);
+        wave_lds_sync();
+        const float rg = tile_rowsum(tG, lane), rb = tile_rowsum(tH, lane);
+        wave_lds_sync();
+        cmb.rows_merged(acc, rs[0], rs[W / 32 - 1], W == 64, Ly::g_wo, rg, rb, Ly::g_lng, Ly::g_lnb, C, sdy,
+                        Ly::g_bo);
+      }
       sg += xor32(sg);
       sgx += xor32(sgx);
       const float mg = sg * (1.0f / C), mgx = sgx * (1.0f / C);
@@ -933,7 +1016,8 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
       for (int r = 0; r < RC; ++r)
         gx[r] = rstd * (sp[Ly::s_lng + chan(r, h)] * gz[r] - mg - xh[r] * mgx);
     } else {
-      cmb.rows_merged(acc, rs[0], rs[W / 32 - 1], W == 64, Ly::g_wo, 0.0f, 0.0f, -1, -1, 0, sdy, Ly::g_bo);
+      if constexpr (!kOwn)
+        cmb.rows_merged(acc, rs[0], rs[W / 32 - 1], W == 64, Ly::g_wo, 0.0f, 0.0f, -1, -1, 0, sdy, Ly::g_bo);
 #pragma unroll
       for (int r = 0; r < RC; ++r) gx[r] = gz[r];
     }
@@ -950,6 +1034,43 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
   if (lane == 0) atomicMax(b.rec_max_bits, vbits);
   bad |= vbits >= 0x7F800000u;
 
+  if constexpr (kOwn) {   // the block's dense gradient from the waves' registers, in a fixed order
+    __syncthreads();                            // the slots are free
+    for (int e2 = threadIdx.x; e2 < nd_pad; e2 += blockDim.x) acc[e2] = 0.0f;
+    __syncthreads();
+    const int m = lane & 31;
+#pragma unroll
+    for (int k = 1; k < D; ++k) {               // hidden layers: each tile has one owner
+      const int mb = wv >> 1, nb = wv & 1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[Ly::gW(k) + (32 * mb + chan(r, h)) * W + 32 * nb + m] = ownW[k][r];
+    }
+    for (int pass = 0; pass < 2; ++pass) {      // layer 0: waves 0, 1, then 2, 3 add their halves
+      if ((wv >> 1) == pass && m < C) {
+        const int mb = wv & 1;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[Ly::gW(0) + (32 * mb + chan(r, h)) * C + m] += ownW[0][r];
+      }
+      __syncthreads();
+    }
+    for (int q = 0; q < kWavesPerBlock; ++q) {  // the row sums, wave by wave
+      if (wv == q && lane < 32) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          acc[Ly::gb(k) + lane] += ownB[k][0];
+          acc[Ly::gb(k) + 32 + lane] += ownB[k][1];
+        }
+        acc[Ly::g_wo + lane] += ownWo[0];
+        acc[Ly::g_wo + 32 + lane] += ownWo[1];
+        if (a.layernorm && lane < C) {
+          acc[Ly::g_lng + lane] += ownLg;
+          acc[Ly::g_lnb + lane] += ownLb;
+        }
+        if (lane == 0) acc[Ly::g_bo] += ownBo;
+      }
+      __syncthreads();
+    }
+  }
   __syncthreads();
   for (int e2 = threadIdx.x; e2 < nd_pad; e2 += blockDim.x) {
     const float v = acc[e2];
@@ -1709,7 +1830,7 @@ static KernelSet make_set() {
   ks.enc = reinterpret_cast<const void*>(&k_enc<L, P>);
   ks.fwd_lds = Ly::s_n * sizeof(float);
   const int nd_pad = (Ly::g_n + 3) & ~3;
-  ks.bwd_lds = (Ly::s_n + nd_pad + kWavesPerBlock * 2 * 32 * kTile) * sizeof(float);
+  ks.bwd_lds = (Ly::s_n + bwd_tiles_lds<W>(nd_pad)) * sizeof(float);
   ks.n_dense = Ly::g_n;
   ks.nd_pad = nd_pad;
   ks.valid = true;

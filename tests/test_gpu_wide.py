@@ -1,0 +1,68 @@
+"""The 64-wide network (MLP 4 x 64, the network of the Mapping Consistency Initialization runs)
+against the oracle: the gradient of every parameter from nic_backward.
+
+The backward pass forms the LayerNorm + MLP gradient of a block over all its chunks before
+writing it out, so these cases give every block several chunks (288 rays x 192 samples = 432
+chunks of 128 points over the 256 blocks of the 64-wide kernel; tiny64: 1024 rays x 64 samples =
+512 chunks) and compare each part of the dense gradient on its own (LayerNorm gain and bias, every
+layer's weights and bias, the output weights and bias), so that a tile written to the wrong place
+shows in its own part.  The upstream gradient is random and set to zero on the rays holding a
+point whose ReLU gate FP32 cannot decide (as in the full-batch test).  Precision form: the same
+gradients against the oracle within the bounds of the precision test.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2506_19742_amd import nic, synth  # noqa: E402
+from test_gpu_fullbatch import GATE_TAU, _gate_margins, _threads  # noqa: E402
+from test_gpu_parity import GRAD_TOL, ocfg, random_params, rel  # noqa: E402
+from test_gpu_precision import BOUNDS  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _parts(oc, ora, nt):
+    """(name, slice) of the dense gradient, offsets into the flat parameter vector."""
+    lay = ora.dense_layout(oc)
+    return [(k, slice(nt + v[0], nt + v[0] + v[1])) for k, v in lay.items() if k != "n"]
+
+
+@pytest.mark.parametrize("workload,precision", [("ct256", 0), ("tiny64", 0), ("ct256", 1)])
+def test_wide_network_backward_matches_oracle(ora, workload, precision):
+    w = synth.WORKLOADS[workload]
+    R = 288 if workload == "ct256" else w.rays
+    cfg = nic.config_for(w, mlp_width=64, mlp_depth=4, rays_per_step=R, seed=90, precision=precision)
+    print(f"[case] wide network {workload} precision {precision}: scan", flush=True)
+    _, g, A = synth.scan(w)
+    oc = ocfg(ora, cfg)
+    m = nic.Model(cfg, g)
+    m.set_projections(torch.tensor(A, device="cuda"))
+    p = random_params(ora, oc, 91, 0.05)
+    m.load_params(p)
+    nt, nd, do = m.n_params()
+    v = 11
+    pix, jit = synth.ray_batch(92, g.n_pix, R, w.samples)
+    ang = float(g.angles[v])
+    dA = np.random.default_rng(93).standard_normal(R).astype(np.float32).astype(np.float64) / R
+    ora.set_threads(_threads())
+    try:
+        _, marg = _gate_margins(ora, oc, g, p, ang, pix, jit)
+        free = marg.min(1) >= GATE_TAU
+        print(f"[case] wide network: {int(free.sum())} of {R} rays free of undecided gates", flush=True)
+        assert free.sum() >= 0.75 * R
+        dA[~free] = 0.0
+        m.zero_grad()
+        m.backward(v, torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda"),
+                   torch.tensor(dA, dtype=torch.float32, device="cuda"))
+        gg = m.flat(m.tensors()[1])
+        _, _, og = ora.ray_batch(oc, g, p, ang, A[v], pix, jit, dA=dA)
+    finally:
+        ora.set_threads(1)
+        m.close()
+    tol = GRAD_TOL if precision == 0 else BOUNDS["grad_dense"]
+    assert rel(gg[:nt], og[:nt]) <= (GRAD_TOL if precision == 0 else BOUNDS["grad_table"])
+    for name, sl in _parts(oc, ora, nt):
+        assert np.abs(og[sl]).max() > 0, name
+        assert rel(gg[sl], og[sl]) <= tol, (name, rel(gg[sl], og[sl]))
