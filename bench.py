@@ -269,7 +269,7 @@ def stats_summary(d: str):
     print(f"\nKernel sources sha256[:16] at measurement: `{kernel_source_sha()}`.")
 
 
-def converge(n_pre: int = 16, n_heldout: int = 4, cap: int = 3000, eval_every: int = 50, target: float = 30.0,
+def converge(n_pre: int = 16, n_heldout: int = 8, cap: int = 3000, eval_every: int = 50, target: float = 30.0,
              log=None) -> dict:
     """Seconds (and steps) to 30 dB PSNR on held-out 256^3 phantoms, BF16 form + Mapping Consistency
     Initialization against plain FP32 with random initialisation (Sec. 2.4, Eq. 2; Sec. 3.1), every
@@ -476,7 +476,7 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the largest workload (512^3, precision form: training and full-volume inference)")
     ap.add_argument("--converge-pre", type=int, default=16, help="MCI pre-training phantoms")
-    ap.add_argument("--converge-heldout", type=int, default=4, help="held-out phantoms per arm")
+    ap.add_argument("--converge-heldout", type=int, default=8, help="held-out phantoms per arm")
     ap.add_argument("--render", type=int, default=0,
                     help="also time forward-only inference of the full n^3 volume (voxel centres)")
     ap.add_argument("--copy-calibration", action="store_true",
