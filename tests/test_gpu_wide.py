@@ -6,9 +6,13 @@ writing it out, so these cases give every block several chunks (288 rays x 192 s
 chunks of 128 points over the 256 blocks of the 64-wide kernel; tiny64: 1024 rays x 64 samples =
 512 chunks) and compare each part of the dense gradient on its own (LayerNorm gain and bias, every
 layer's weights and bias, the output weights and bias), so that a tile written to the wrong place
-shows in its own part.  The upstream gradient is random and set to zero on the rays holding a
-point whose ReLU gate FP32 cannot decide (as in the full-batch test).  Precision form: the same
-gradients against the oracle within the bounds of the precision test.
+shows in its own part; also with the LayerNorm off (plain hash encoding).  The upstream gradient
+is random and set to zero on the rays holding a
+point whose ReLU gate FP32 cannot decide (as in the full-batch test).  Precision form: the dense
+gradient within the precision test's bound; the table gradient, whose data-gradient chain runs
+through four 64-wide BF16 products here (three 32-wide in the precision test), within 0.25 (0.15
+measured at tiny64, the same before and after the change to the weight gradients' accumulation,
+which the table gradient does not pass through).
 """
 import numpy as np
 import pytest
@@ -29,17 +33,21 @@ def _parts(oc, ora, nt):
     return [(k, slice(nt + v[0], nt + v[0] + v[1])) for k, v in lay.items() if k != "n"]
 
 
-@pytest.mark.parametrize("workload,precision", [("ct256", 0), ("tiny64", 0), ("ct256", 1)])
-def test_wide_network_backward_matches_oracle(ora, workload, precision):
+@pytest.mark.parametrize("workload,precision,ln", [("ct256", 0, 1), ("tiny64", 0, 1), ("ct256", 1, 1),
+                                                   ("tiny64", 1, 1), ("ct256", 0, 0)])
+def test_wide_network_backward_matches_oracle(ora, workload, precision, ln):
     w = synth.WORKLOADS[workload]
     R = 288 if workload == "ct256" else w.rays
-    cfg = nic.config_for(w, mlp_width=64, mlp_depth=4, rays_per_step=R, seed=90, precision=precision)
-    print(f"[case] wide network {workload} precision {precision}: scan", flush=True)
+    cfg = nic.config_for(w, mlp_width=64, mlp_depth=4, rays_per_step=R, seed=90, precision=precision,
+                         layernorm=ln)
+    print(f"[case] wide network {workload} precision {precision} layernorm {ln}: scan", flush=True)
     _, g, A = synth.scan(w)
     oc = ocfg(ora, cfg)
     m = nic.Model(cfg, g)
     m.set_projections(torch.tensor(A, device="cuda"))
-    p = random_params(ora, oc, 91, 0.05)
+    # without LayerNorm the network sees the raw encoding: table entries of order 1 keep its hidden
+    # pre-activations of order 1, as the LayerNorm output is, so few of their ReLU gates are undecided
+    p = random_params(ora, oc, 91, 0.05 if ln else 1.0)
     m.load_params(p)
     nt, nd, do = m.n_params()
     v = 11
@@ -51,7 +59,7 @@ def test_wide_network_backward_matches_oracle(ora, workload, precision):
         _, marg = _gate_margins(ora, oc, g, p, ang, pix, jit)
         free = marg.min(1) >= GATE_TAU
         print(f"[case] wide network: {int(free.sum())} of {R} rays free of undecided gates", flush=True)
-        assert free.sum() >= 0.75 * R
+        assert free.sum() >= (0.75 if ln else 0.5) * R   # raw encodings leave more gates near zero
         dA[~free] = 0.0
         m.zero_grad()
         m.backward(v, torch.tensor(pix, device="cuda"), torch.tensor(jit, device="cuda"),
@@ -62,7 +70,12 @@ def test_wide_network_backward_matches_oracle(ora, workload, precision):
         ora.set_threads(1)
         m.close()
     tol = GRAD_TOL if precision == 0 else BOUNDS["grad_dense"]
-    assert rel(gg[:nt], og[:nt]) <= (GRAD_TOL if precision == 0 else BOUNDS["grad_table"])
+    print(f"[case] table gradient rel {rel(gg[:nt], og[:nt]):.3e}; dense parts "
+          + ", ".join(f"{k} {rel(gg[sl], og[sl]):.2e}" for k, sl in _parts(oc, ora, nt)), flush=True)
+    assert rel(gg[:nt], og[:nt]) <= (GRAD_TOL if precision == 0 else 0.25)
     for name, sl in _parts(oc, ora, nt):
+        if not ln and name in ("ln_g", "ln_b"):   # no LayerNorm: no gradient there on either side
+            assert np.abs(gg[sl]).max() == 0 and np.abs(og[sl]).max() == 0, name
+            continue
         assert np.abs(og[sl]).max() > 0, name
         assert rel(gg[sl], og[sl]) <= tol, (name, rel(gg[sl], og[sl]))
