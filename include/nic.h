@@ -319,8 +319,8 @@ int32_t nic_encoder_level_major(const nic_model* m);
  * by a pair of HIP events on the model's stream.  nic_kernel_times synchronises the stream and
  * returns, per kernel kind k (0 rays, 1 forward, 2 backward, 3 encode (the level-major encoder),
  * 4 adam, 5 bin scan, 6 bin reduce, which includes the dense reduction), the total milliseconds
- * ms[k] and the number of launches calls[k] since timing was enabled; ms and calls must hold 8
- * entries (*count = 7). */
+ * ms[k] and the number of launches calls[k] since timing was enabled; ms and calls must hold at
+ * least 7 entries (*count = 7, the number written). */
 nic_status nic_set_timing(nic_model* m, int32_t enable);
 nic_status nic_kernel_times(nic_model* m, double* ms, int64_t* calls, int32_t* count);
 
