@@ -1,7 +1,7 @@
 """Non-finite inputs and the output-activation alternatives, through the C ABI.
 
 A NaN or infinite value that reaches a training step (through the projections, an upstream
-gradient or a target volume) must leave the model bitwise as it was: no parameter, Adam moment,
+gradient or a target volume; with either encoder placement) must leave the model bitwise as it was: no parameter, Adam moment,
 gradient or FP16 table entry changes, and the next synchronising call reports NIC_ENONFINITE with
 the step counter back at the first skipped step.  Projections are checked when they are set.
 The identity and softplus heads (threshold 20) are compared with the FP64 oracle like the sigmoid
@@ -31,13 +31,19 @@ def _unchanged(model, snap):
         assert torch.equal(a, b), f"tensor {k} changed"
 
 
-@pytest.fixture(scope="module", params=[0, 1], ids=["fp32", "bf16"])
+@pytest.fixture(scope="module", params=[(0, "in_forward"), (1, "in_forward"), (0, "level_major"), (1, "level_major")],
+                ids=["fp32", "bf16", "fp32-level-major", "bf16-level-major"])
 def case(request):
+    """tiny64 encodes inside the forward kernel by default; the level-major encoder (the default of
+    the larger tables) is forced in the last two cases."""
+    prec, placement = request.param
     w = synth.WORKLOADS["tiny64"]
-    cfg = nic.config_for(w, seed=5, precision=request.param)
+    cfg = nic.config_for(w, seed=5, precision=prec)
     _, g, A = synth.scan(w)
-    print(f"[case] non-finite tiny64 precision {request.param}", flush=True)
+    print(f"[case] non-finite tiny64 precision {prec} encoder {placement}", flush=True)
     m = nic.Model(cfg, g)
+    m.set_encoder_placement(placement)
+    assert m.encoder_level_major() == (placement == "level_major")
     proj = torch.tensor(A, device="cuda")
     m.set_projections(proj)
     m.train(3, want_loss=False)                    # moments away from zero
