@@ -1460,10 +1460,18 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
     // while the current one is added (two record buffers taking turns, so no register copies wait
     // for loads); a segment ends (barrier, flush, barrier) wherever its bin ends.  Record loads are
     // unpredicated (positions past re re-read record re - 1, which is never added) so that the wait
-    // for the current chunk leaves the next chunk's loads outstanding.
+    // for the current chunk leaves the next chunk's loads outstanding.  Each record is read exactly
+    // once, so the loads are non-temporal: the stream then does not evict the parameters, moments
+    // and table lines of the flushes and of the next step's encoder from the L2s and the memory-side
+    // cache.
     auto load = [&](BinRec (&buf)[U], uint32_t cb) {
 #pragma unroll
-      for (int k = 0; k < U; ++k) buf[k] = a.recs[min(cb + k * kReduceThreads + threadIdx.x, re - 1)];
+      for (int k = 0; k < U; ++k) {
+        const BinRec* r = a.recs + min(cb + k * kReduceThreads + threadIdx.x, re - 1);
+        buf[k].idx = __builtin_nontemporal_load(&r->idx);
+        buf[k].v0 = __builtin_nontemporal_load(&r->v0);
+        buf[k].v1 = __builtin_nontemporal_load(&r->v1);
+      }
     };
     auto add_chunk = [&](const BinRec (&cur)[U], uint32_t cb) {
       const uint32_t ce = min(re, cb + CH);
