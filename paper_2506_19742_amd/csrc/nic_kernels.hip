@@ -725,11 +725,13 @@ __global__ void __launch_bounds__(kEncThreads) k_enc(const FwdArgs a) {
         for (int k = 0; k < 8; ++k) atomicAdd(hist + ((idx[k] >> T.bin_shift) - b0), 1u);
       }
     }
+    // Stored non-temporally: each half-wave writes one whole 128-B line per channel, and keeping
+    // the encoding out of the L2 leaves the L2 to the level's table.
     const int64_t wid = p / kPtsPerWave;
     if (wid * kPtsPerWave < a.n_points) {
       float* dst = a.enc_out + (wid * RC + r0) * kWave + ln + 32 * hh;
-      dst[0] = s0;
-      dst[kWave] = s1;
+      __builtin_nontemporal_store(s0, dst);
+      __builtin_nontemporal_store(s1, dst + kWave);
     }
   }
   __syncthreads();
