@@ -293,6 +293,8 @@ struct nic_model {
   bool timing = false;
   int32_t enc_placement = NIC_ENCODER_AUTO;   // where ray training steps on one table encode
   bool level_major_pays = false;              // the auto rule for this model on this device
+  const RaysArgs* next_rays = nullptr;        // set by nic_train: the next step's rays, drawn by this
+                                              // step's k_bin_combine
   int64_t rec_cap = 0;        // capacity of recs (records)
   uint32_t* edge = nullptr;
   int32_t *ebeg = nullptr, *esrc = nullptr;
@@ -358,8 +360,8 @@ FwdArgs fwd_args(nic_model* m, int mode, int64_t n_points) {
   return a;
 }
 
-nic_status rays(nic_model* m, int32_t view, const int32_t* pix_in, int32_t n_rays, uint32_t step, int32_t* pix_out,
-                float* jitter_out) {
+RaysArgs rays_args(const nic_model* m, int32_t view, const int32_t* pix_in, int32_t n_rays, uint32_t step,
+                   int32_t* pix_out, float* jitter_out) {
   RaysArgs r{};
   r.geo = m->geo;
   r.ca = m->ca[view];
@@ -376,6 +378,12 @@ nic_status rays(nic_model* m, int32_t view, const int32_t* pix_in, int32_t n_ray
   r.rays = m->rays;
   r.pix_out = pix_out;
   r.jitter_out = jitter_out;
+  return r;
+}
+
+nic_status rays(nic_model* m, int32_t view, const int32_t* pix_in, int32_t n_rays, uint32_t step, int32_t* pix_out,
+                float* jitter_out) {
+  const RaysArgs r = rays_args(m, view, pix_in, n_rays, step, pix_out, jitter_out);
   KTimer kt(m, 0);
   NIC_HIP(launch_rays(r, m->stream));
   return NIC_OK;
@@ -501,6 +509,10 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
     d.v = m->v + pl.dense_off;
     d.bad_step = m->bad_step;
     br.dense_blocks = (d.nd + 63) / 64;
+    if (m->next_rays) {
+      br.next_rays = *m->next_rays;
+      br.ray_blocks = (br.next_rays.n_rays + 1023) / 1024;
+    }
     NIC_HIP(launch_bin_reduce(br, m->reduce_grid, m->stream));
   }
   if (fused) m->step += 1;
@@ -913,14 +925,26 @@ nic_status nic_train(nic_model* m, int32_t n_steps, float* loss_host) {
   if (!m->proj) return fail(NIC_ESTATE, "projections not set");
   bool bad = false;
   nic_status st = NIC_OK;
+  const int32_t R = m->cfg.rays_per_step;
+  bool drawn = false;   // this step's rays were drawn by the previous step's combine kernel
   for (int32_t k0 = 0; k0 < n_steps; k0 += kLossHist) {
     const int32_t kn = std::min<int32_t>(kLossHist, n_steps - k0);
     for (int32_t k = 0; k < kn; ++k) {
-      const int32_t view = nic_view_for_step(m, m->step);
-      st = rays(m, view, nullptr, m->cfg.rays_per_step, (uint32_t)m->step, nullptr, nullptr);
+      const int64_t t = m->step;
+      if (!drawn) {
+        st = rays(m, nic_view_for_step(m, t), nullptr, R, (uint32_t)t, nullptr, nullptr);
+        if (st) return st;
+      }
+      // a step that is not the call's last draws the next step's rays (step t + 1) in its combine
+      // kernel, once its backward pass no longer reads the ray buffer
+      const bool more = k0 + k + 1 < n_steps;
+      RaysArgs next{};
+      if (more) next = rays_args(m, nic_view_for_step(m, t + 1), nullptr, R, (uint32_t)(t + 1), nullptr, nullptr);
+      m->next_rays = more ? &next : nullptr;
+      st = ray_train_step(m, R, nullptr, m->loss + k);   // advances m->step to t + 1
+      m->next_rays = nullptr;
       if (st) return st;
-      st = ray_train_step(m, m->cfg.rays_per_step, nullptr, m->loss + k);
-      if (st) return st;
+      drawn = more;
     }
     if (loss_host) {
       NIC_HIP(hipMemcpyAsync(loss_host + k0, m->loss, kn * sizeof(float), hipMemcpyDeviceToHost, m->stream));

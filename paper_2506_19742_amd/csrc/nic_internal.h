@@ -170,6 +170,10 @@ struct BinReduceArgs {
   const uint32_t* bad_step;       // non-zero: a non-finite value was met, nothing is written
   DenseReduceArgs dense;
   int32_t dense_blocks;           // (dense.nd + 63) / 64 extra k_bin_combine blocks
+  // The next training step's ray batch, drawn by ray_blocks = ceil(n_rays / 1024) k_bin_combine
+  // blocks placed first (none when next_rays.n_rays == 0): the ray buffer is free once k_bwd is done.
+  RaysArgs next_rays;
+  int32_t ray_blocks;
 };
 hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s);
 size_t bin_reduce_lds();

@@ -1,7 +1,12 @@
 // Kernels of the training step for gfx950 (one MI355X).
 //
-// Step = k_rays -> k_fwd -> bin scan -> k_bwd -> k_bin_reduce -> k_bin_combine on the model's stream.
+// Step = k_rays -> [k_enc ->] k_fwd -> bin scan -> k_bwd -> k_bin_reduce -> k_bin_combine on the
+// model's stream.
 //  k_rays   one thread per ray slot: pixel (given or Philox/Feistel draw), FP64 ray setup, A_gt.
+//           Within a multi-step training call the first blocks of each step's k_bin_combine draw
+//           the next step's rays instead.
+//  k_enc    (ray training on one table whose levels fit an XCD's L2) level-major hash encoding,
+//           one level per XCD at a time, and the per-bin record counts; k_fwd then reads it.
 //  k_fwd    four waves per block, 32 points per wave, two lanes per point (lane half h handles
 //           half of the levels): sample position -> hash encode (8 corner gathers per level) ->
 //           LayerNorm -> MLP on v_mfma_f32_32x32x2f32 -> mu -> per-wave partial ray sum of
@@ -1087,9 +1092,8 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_bwd(const FwdArgs a
 // ---------------------------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------------------------
-__global__ void k_rays(const RaysArgs a) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= a.n_rays) return;
+// Ray r of a batch: pixel (given or drawn), FP64 set-up, measured line integral.
+__device__ __forceinline__ void ray_one(const RaysArgs& a, int r) {
   const int32_t pix = a.pix_in ? a.pix_in[r] : draw_pixel(a.seed, a.step, a.h_bits, a.n_pix, (uint32_t)r);
   RayRec rec;
   const bool in_range = pix >= 0 && (uint32_t)pix < a.n_pix;
@@ -1104,6 +1108,11 @@ __global__ void k_rays(const RaysArgs a) {
   if (a.pix_out) a.pix_out[r] = pix;
   if (a.jitter_out)
     for (int i = 0; i < a.N; ++i) a.jitter_out[(size_t)r * a.N + i] = jitter(a.seed, a.step, (uint32_t)r, (uint32_t)i);
+}
+
+__global__ void k_rays(const RaysArgs a) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < a.n_rays) ray_one(a, r);
 }
 
 // A_pred of each ray from the per-wave partial sums (fixed order).
@@ -1549,20 +1558,27 @@ __global__ void __launch_bounds__(kReduceThreads) k_bin_reduce(const BinReduceAr
 // record block_start[j] when that bin starts inside block j - 1's range, adds the int64 slots of the
 // blocks j0 = j - 1 .. j1 that hold part of it in order, and adds the result to the FP32 gradient.
 // Each such block j is kCombineParts blocks here, part k taking the k-th part of every tile (short
-// chains of loads per thread instead of eight entries each), and the grid is kCombineParts x the
-// reduction's grid G followed by a.dense_blocks blocks of the dense gradient reduction.
+// chains of loads per thread instead of eight entries each), and the grid is a.ray_blocks blocks
+// drawing the next training step's rays, then kCombineParts x the reduction's grid G, then
+// a.dense_blocks blocks of the dense gradient reduction.
 __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
   constexpr int NB = 1 << kBinBits, QP = NB / kCombineParts;
   __shared__ float red[1024];
-  const int GP = gridDim.x - a.dense_blocks, G = GP / kCombineParts;
-  if ((int)blockIdx.x >= GP) {   // block-uniform
-    dense_reduce_block(a.dense, blockIdx.x - GP, red);
+  if ((int)blockIdx.x < a.ray_blocks) {   // the next training step's rays (block-uniform)
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < a.next_rays.n_rays) ray_one(a.next_rays, r);
+    return;
+  }
+  const int bx = (int)blockIdx.x - a.ray_blocks;
+  const int GP = (int)gridDim.x - a.ray_blocks - a.dense_blocks, G = GP / kCombineParts;
+  if (bx >= GP) {   // block-uniform
+    dense_reduce_block(a.dense, bx - GP, red);
     return;
   }
   if (*a.bad_step) return;   // non-finite step: write nothing (block-uniform)
-  const int part = blockIdx.x % kCombineParts, q0 = part * QP;
+  const int part = bx % kCombineParts, q0 = part * QP;
   if (a.fused) {   // bins without records: Adam with a zero gradient (dense Adam semantics)
-    for (int B = blockIdx.x / kCombineParts; B < a.n_bins; B += G) {
+    for (int B = bx / kCombineParts; B < a.n_bins; B += G) {
       if (a.bin_start[B] != a.bin_start[B + 1]) continue;
       for (int sub = 0; sub < a.n_sub; ++sub) {
         const uint32_t base = ((uint32_t)B << a.bin_shift) + ((uint32_t)sub << kBinBits);
@@ -1582,7 +1598,7 @@ __global__ void __launch_bounds__(1024) k_bin_combine(const BinReduceArgs a) {
   }
   const uint64_t T = a.bin_start[a.n_bins];
   const uint64_t Ge = T < (uint64_t)G ? T : (uint64_t)G;
-  const uint64_t jb = blockIdx.x / kCombineParts;
+  const uint64_t jb = bx / kCombineParts;
   if (jb == 0 || jb >= Ge) return;
   const uint32_t rs = a.block_start[jb], rs_prev = a.block_start[jb - 1];
   if (rs >= T) return;
@@ -1958,9 +1974,10 @@ hipError_t launch_bin_reduce(const BinReduceArgs& a, int grid, hipStream_t s) {
   if (a.bin_shift < kBinBits || a.bin_shift > 31 || a.n_sub != (1 << (a.bin_shift - kBinBits)))
     return hipErrorInvalidValue;
   if (a.dense_blocks != (a.dense.nd + 63) / 64) return hipErrorInvalidValue;
+  if (a.ray_blocks != (a.next_rays.n_rays + 1023) / 1024) return hipErrorInvalidValue;
   if (a.fused) k_bin_reduce<true><<<grid, kReduceThreads, bin_reduce_lds(), s>>>(a);
   else k_bin_reduce<false><<<grid, kReduceThreads, bin_reduce_lds(), s>>>(a);
-  k_bin_combine<<<kCombineParts * grid + a.dense_blocks, 1024, 0, s>>>(a);
+  k_bin_combine<<<a.ray_blocks + kCombineParts * grid + a.dense_blocks, 1024, 0, s>>>(a);
   return hipGetLastError();
 }
 
