@@ -445,6 +445,11 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
     f.enc_pre = m->enc;
     f.enc_out = nullptr;
     f.bin_counts = nullptr;
+    f.scan_counts = m->counts;   // k_fwd also runs the offsets' row scans of k_enc's counts
+    f.scan_rel = m->offs;
+    f.scan_totals = m->totals;
+    f.edge_beg = m->ebeg;
+    f.edge_src = m->esrc;
     KTimer kt(m, 1);
     NIC_HIP(launch_fwd(pl.ks, f, grid, 0, m->stream));
   } else {
@@ -455,7 +460,7 @@ nic_status fwd_bwd(nic_model* m, FwdArgs a, BwdArgs b, const float* loss_src, in
     KTimer kt(m, 5);
     NIC_HIP(launch_bin_scan(m->counts, pl.n_bins, grid, m->offs, m->totals, m->bin_start, m->block_start,
                             m->block_first_bin, m->reduce_grid, m->rec_max, lvl ? m->edge : nullptr, m->ebeg,
-                            m->esrc, m->stream));
+                            m->esrc, lvl, m->stream));
   }
   b.enc_in = m->enc;
   b.a_pred_out = m->apred;

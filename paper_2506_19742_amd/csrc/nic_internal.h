@@ -41,6 +41,13 @@ struct FwdArgs {
   // level boundary can hold entries of several levels; the bin scan adds these rows)
   int32_t enc_grid;
   uint32_t* edge_counts;
+  // k_fwd reading k_enc's encoding: the record offsets' row scans of k_enc's counts (bin_row_scan
+  // over bins blockIdx, blockIdx + gridDim, ...; no separate k_bin_rowscan), or scan_rel == NULL
+  const uint32_t* scan_counts;
+  uint32_t* scan_rel;
+  uint32_t* scan_totals;
+  const int32_t* edge_beg;
+  const int32_t* edge_src;
   // voxel-loss mode (pre-training): point p uses table p / pts_per_table, whose entries start at
   // (p / pts_per_table) * table_stride, and the target volume of that table
   int64_t pts_per_table;
@@ -129,7 +136,7 @@ hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const 
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
                            uint32_t* bin_start, uint32_t* block_start, int32_t* block_first_bin, int reduce_grid,
                            uint32_t* rec_max_bits, const uint32_t* edge, const int32_t* edge_beg,
-                           const int32_t* edge_src, hipStream_t s);
+                           const int32_t* edge_src, bool rows_done, hipStream_t s);
 // Dense (LayerNorm + MLP) gradient reduction run by the last blocks of k_bin_combine.
 struct DenseReduceArgs {
   const float* partials;   // [n_blocks][nd_pad] per-block partial sums from k_bwd

@@ -569,6 +569,52 @@ __device__ __forceinline__ void mlp_forward(const float* sp, const float* z, flo
   }
 }
 
+// Record offsets, step 1, for bin b (one 256-thread block; every thread calls it): exclusive scan of
+// the bin's per-block counts -> offsets relative to the bin's first record; the bin's total.  part:
+// 4 words of LDS.
+__device__ void bin_row_scan(int b, const uint32_t* __restrict__ counts, int grid, uint32_t* __restrict__ rel,
+                             uint32_t* __restrict__ totals, const uint32_t* __restrict__ edge,
+                             const int32_t* __restrict__ edge_beg, const int32_t* __restrict__ edge_src,
+                             uint32_t* part) {
+  const int t = threadIdx.x;
+  const int per = (grid + 255) / 256;
+  const int w0 = t * per, w1 = min(grid, w0 + per);
+  const uint32_t* row = counts + (size_t)b * grid;
+  const int e0 = edge ? edge_beg[b] : 0, e1 = edge ? edge_beg[b + 1] : 0;
+  auto count = [&](int w) -> uint32_t {   // a bin at a level boundary: the levels' edge rows
+    if (e0 == e1) return row[w];
+    uint32_t v = 0u;
+    for (int k = e0; k < e1; ++k) v += edge[(size_t)edge_src[k] * grid + w];
+    return v;
+  };
+  uint32_t s = 0;
+  for (int w = w0; w < w1; ++w) s += count(w);
+  // inclusive scan within the wave, then the four waves' totals through LDS
+  const int lane = t & 63, wv = t >> 6;
+  uint32_t inc = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
+  }
+  if (lane == 63) part[wv] = inc;
+  __syncthreads();
+  uint32_t before = 0u, total = 0u;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t v = part[q];
+    before += q < wv ? v : 0u;
+    total += v;
+  }
+  uint32_t run = before + inc - s;
+  for (int w = w0; w < w1; ++w) {
+    rel[(size_t)b * grid + w] = run;
+    run += count(w);
+  }
+  if (t == 0) totals[b] = total;
+  __syncthreads();   // part is written again by the next call
+}
+
 // ---------------------------------------------------------------------------------------------
 // Forward kernel
 // ---------------------------------------------------------------------------------------------
@@ -584,6 +630,13 @@ __global__ void __launch_bounds__(kBlock, W == 32 ? 2 : 1) k_fwd(const FwdArgs a
   if (hist)
     for (int b2 = threadIdx.x; b2 < a.n_bins; b2 += blockDim.x) hist[b2] = 0u;
   __syncthreads();
+  if constexpr (PRE) {   // the record offsets' row scans of the encoder's counts, bins spread over the grid
+    __shared__ uint32_t part[kBlock / 64];
+    if (a.scan_rel)
+      for (int b2 = blockIdx.x; b2 < a.n_bins; b2 += gridDim.x)
+        bin_row_scan(b2, a.scan_counts, a.enc_grid, a.scan_rel, a.scan_totals, a.edge_counts, a.edge_beg,
+                     a.edge_src, part);
+  }
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
   const int64_t n_chunks = (a.n_points + kPtsPerBlock - 1) / kPtsPerBlock;
@@ -1254,41 +1307,13 @@ __global__ void k_init(float* __restrict__ params, int64_t n_table, int64_t dens
   }
 }
 
-// Record offsets, step 1 (one block per bin): exclusive scan of the bin's per-block counts ->
-// offsets relative to the bin's first record; the bin's total.
 __global__ void __launch_bounds__(256) k_bin_rowscan(const uint32_t* __restrict__ counts, int grid,
                                                      uint32_t* __restrict__ rel, uint32_t* __restrict__ totals,
                                                      const uint32_t* __restrict__ edge,
                                                      const int32_t* __restrict__ edge_beg,
                                                      const int32_t* __restrict__ edge_src) {
-  __shared__ uint32_t part[256];
-  const int b = blockIdx.x, t = threadIdx.x;
-  const int per = (grid + 255) / 256;
-  const int w0 = t * per, w1 = min(grid, w0 + per);
-  const uint32_t* row = counts + (size_t)b * grid;
-  const int e0 = edge ? edge_beg[b] : 0, e1 = edge ? edge_beg[b + 1] : 0;
-  auto count = [&](int w) -> uint32_t {   // a bin at a level boundary: the levels' edge rows
-    if (e0 == e1) return row[w];
-    uint32_t v = 0u;
-    for (int k = e0; k < e1; ++k) v += edge[(size_t)edge_src[k] * grid + w];
-    return v;
-  };
-  uint32_t s = 0;
-  for (int w = w0; w < w1; ++w) s += count(w);
-  part[t] = s;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const uint32_t v = t >= o ? part[t - o] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  uint32_t run = part[t] - s;
-  for (int w = w0; w < w1; ++w) {
-    rel[(size_t)b * grid + w] = run;
-    run += count(w);
-  }
-  if (t == 255) totals[b] = part[255];
+  __shared__ uint32_t part[4];
+  bin_row_scan(blockIdx.x, counts, grid, rel, totals, edge, edge_beg, edge_src, part);
 }
 
 // Record offsets, step 2 (one block): bin starts (exclusive scan of the bin totals, with the total T
@@ -1962,8 +1987,8 @@ hipError_t launch_init(float* params, int64_t n_table, int64_t dense_off, const 
 hipError_t launch_bin_scan(const uint32_t* counts, int n_bins, int grid, uint32_t* rel, uint32_t* totals,
                            uint32_t* bin_start, uint32_t* block_start, int32_t* block_first_bin, int reduce_grid,
                            uint32_t* rec_max_bits, const uint32_t* edge, const int32_t* edge_beg,
-                           const int32_t* edge_src, hipStream_t s) {
-  k_bin_rowscan<<<n_bins, 256, 0, s>>>(counts, grid, rel, totals, edge, edge_beg, edge_src);
+                           const int32_t* edge_src, bool rows_done, hipStream_t s) {
+  if (!rows_done) k_bin_rowscan<<<n_bins, 256, 0, s>>>(counts, grid, rel, totals, edge, edge_beg, edge_src);
   k_bin_plan<<<1, 1024, 0, s>>>(totals, n_bins, reduce_grid, bin_start, block_start, block_first_bin, rec_max_bits);
   return hipGetLastError();
 }
