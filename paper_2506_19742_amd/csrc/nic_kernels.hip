@@ -1328,9 +1328,10 @@ __global__ void __launch_bounds__(1024) k_bin_plan(const uint32_t* __restrict__ 
                                                    int32_t* __restrict__ block_first_bin,
                                                    uint32_t* __restrict__ rec_max_bits) {
   if (threadIdx.x == 0) *rec_max_bits = 0u;
-  __shared__ uint32_t part[1024];
-  __shared__ unsigned long long cpart[1024];
-  const int t = threadIdx.x, nt = blockDim.x;
+  constexpr int kWaves = 1024 / 64;
+  __shared__ uint32_t part[kWaves];
+  __shared__ unsigned long long cpart[kWaves];
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6;
   const int per = (n_bins + nt - 1) / nt;
   const int b0 = t * per, b1 = min(n_bins, b0 + per);
   uint32_t srec = 0;
@@ -1340,21 +1341,35 @@ __global__ void __launch_bounds__(1024) k_bin_plan(const uint32_t* __restrict__ 
     srec += tot;
     scost += tot ? (unsigned long long)tot + kFlushCost : 0ull;
   }
-  part[t] = srec;
-  cpart[t] = scost;
-  __syncthreads();
-  for (int o = 1; o < nt; o <<= 1) {
-    const uint32_t ar = t >= o ? part[t - o] : 0u;
-    const unsigned long long ac = t >= o ? cpart[t - o] : 0ull;
-    __syncthreads();
-    part[t] += ar;
-    cpart[t] += ac;
-    __syncthreads();
+  // inclusive scans within each wave, then the waves' totals through LDS
+  uint32_t ir = srec;
+  unsigned long long ic = scost;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t vr = __shfl_up(ir, o, 64);
+    const unsigned long long vc = __shfl_up(ic, o, 64);
+    if (lane >= o) {
+      ir += vr;
+      ic += vc;
+    }
   }
-  const uint64_t T = part[nt - 1], C = cpart[nt - 1];
+  if (lane == 63) {
+    part[wv] = ir;
+    cpart[wv] = ic;
+  }
+  __syncthreads();
+  uint64_t T = 0, C = 0;
+  uint32_t rec = ir - srec;
+  unsigned long long cst = ic - scost;
+  for (int q = 0; q < nt / 64; ++q) {
+    T += part[q];
+    C += cpart[q];
+    if (q < wv) {
+      rec += part[q];
+      cst += cpart[q];
+    }
+  }
   const uint64_t Ge = T < (uint64_t)G ? T : (uint64_t)G;
-  uint32_t rec = part[t] - srec;
-  unsigned long long cst = cpart[t] - scost;
   for (int b = b0; b < b1; ++b) {
     const uint32_t tot = totals[b];
     bin_start[b] = rec;
