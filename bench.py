@@ -142,6 +142,23 @@ def achievable(kt, ab, ceil, traffic, precision, workload):
     return res
 
 
+def timed_steps(model, steps: int) -> None:
+    """steps training steps with HIP events around every kernel of every TIMING_EVERY-th step: each
+    event costs a few us of stream time, so bracketing every step would slow the step it measures by
+    about 4 %.  The steps in between run as one training call, as a caller training for many steps
+    would (within a call each step's combine kernel draws the next step's rays)."""
+    i = 0
+    while i < steps:
+        model.set_timing(True)
+        model.train(1, want_loss=False)
+        i += 1
+        n = min(TIMING_EVERY - 1, steps - i)
+        if n > 0:
+            model.set_timing(False)
+            model.train(n, want_loss=False)
+            i += n
+
+
 KERNEL_KIND = (("k_enc", "encode"), ("k_fwd", "forward"), ("k_bwd", "backward"), ("k_bin_reduce", "bin_reduce"),
                ("k_bin_combine", "bin_reduce"), ("k_adam", "adam"))
 
@@ -375,9 +392,7 @@ def large(steps: int = 50, warmup: int = 10, log=None) -> dict:
     model.train(warmup, want_loss=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
-        model.set_timing(i % TIMING_EVERY == 0)
-        model.train(1, want_loss=False)
+    timed_steps(model, steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kt = model.kernel_times()
@@ -548,11 +563,7 @@ def main():
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        # HIP events around every kernel of every TIMING_EVERY-th step: each event costs a few us of
-        # stream time, so bracketing every step would slow the step it measures by about 4 %
-        model.set_timing(i % TIMING_EVERY == 0)
-        model.train(1, want_loss=False)
+    timed_steps(model, args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kt = model.kernel_times()
