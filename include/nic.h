@@ -172,7 +172,9 @@ nic_status nic_step(nic_model* m, int32_t view, const int32_t* pix_dev, const fl
 /* n_steps training steps with every draw on the device: view order a fresh permutation of the
  * views per epoch of n_views steps, pixels and jitter from Philox.  loss_host: host float32
  * [n_steps] (synchronous; NIC_ENONFINITE if any loss is not finite or a step was skipped, see
- * nic_sync) or NULL (asynchronous; a skipped step is reported by the next check). */
+ * nic_sync) or NULL (asynchronous; a skipped step is reported by the next check).  One call of n
+ * steps equals n calls of one step bit for bit; within a call each step's last kernel also draws
+ * the next step's rays, so a call of many steps saves a launch per step. */
 nic_status nic_train(nic_model* m, int32_t n_steps, float* loss_host);
 
 /* The view nic_train uses at step `step` (host only). */
@@ -317,8 +319,9 @@ int32_t nic_encoder_level_major(const nic_model* m);
 
 /* Kernel timing for benchmarks: with enable != 0, every kernel of the training path is bracketed
  * by a pair of HIP events on the model's stream.  nic_kernel_times synchronises the stream and
- * returns, per kernel kind k (0 rays, 1 forward, 2 backward, 3 encode (the level-major encoder),
- * 4 adam, 5 bin scan, 6 bin reduce, which includes the dense reduction), the total milliseconds
+ * returns, per kernel kind k (0 rays (in nic_train the first step of a call only), 1 forward,
+ * 2 backward, 3 encode (the level-major encoder), 4 adam, 5 bin scan, 6 bin reduce, which includes
+ * the dense reduction and, in nic_train, the next step's ray draw), the total milliseconds
  * ms[k] and the number of launches calls[k] since timing was enabled; ms and calls must hold at
  * least 7 entries (*count = 7, the number written). */
 nic_status nic_set_timing(nic_model* m, int32_t enable);
