@@ -702,6 +702,31 @@ def test_repeated_steps_are_bitwise_reproducible(ora):
     assert torch.equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("workload", ["tiny64", "ct256"])
+def test_train_call_split_is_bitwise(workload):
+    """Within a training call each step's last kernel draws the next step's rays; a call of 7 steps,
+    7 calls of one step and calls of 2 + 5 steps give the same losses, parameters, gradients and
+    Adam moments bit for bit (tiny64 encodes in the forward kernel, ct256 level-major)."""
+    print(f"[case] training call split {workload}", flush=True)
+    w = synth.WORKLOADS[workload]
+    _, g, A = synth.scan(w)
+    proj = torch.tensor(A, device="cuda")
+    runs = []
+    for split in ((7,), (1,) * 7, (2, 5)):
+        m = nic.Model(nic.config_for(w, seed=23), g)
+        m.set_projections(proj)
+        losses = np.concatenate([m.train(k) for k in split])
+        assert m.get_step() == 7
+        runs.append((losses, [None if t is None else t.clone() for t in m.tensors()]))
+        m.close()
+    for losses, ts in runs[1:]:
+        assert np.array_equal(losses, runs[0][0])
+        for k, (x, y) in enumerate(zip(ts, runs[0][1])):
+            assert (x is None) == (y is None), k
+            if x is not None:
+                assert torch.equal(x, y), k
+
+
 def test_checkpoint_resume_is_bitwise(ora):
     """Kill/resume: 3 steps, save, load into a fresh model, 3 more steps == 6 uninterrupted steps."""
     w = synth.WORKLOADS["tiny64"]
