@@ -312,8 +312,10 @@ hipEvent_t ev_get(nic_model* m) {
     m->ev_free.pop_back();
     return e;
   }
+  // timing only (read after the stream has drained): no system-scope fence at each record, which
+  // would write back and invalidate the caches between the kernels it brackets
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
