@@ -7,9 +7,10 @@ by a range boundary leaves its partial tile in slot 2j (the block's first bin) o
 and ``k_bin_combine`` adds the slots of every cut bin in block order.  This file restates that
 logic in Python, step for step with the kernels, and checks on thousands of random bin layouts that
 every record is reduced exactly once, every non-empty bin is either flushed by one block or
-combined once from exactly the slots that were written, and no slot is written twice.  The GPU
-tests check the kernels themselves (parity with the oracle, and bit-identical steps for different
-reduction grids).
+combined once from exactly the slots that were written, and no slot is written twice.  It also
+restates the wave scans that form the record offsets (``bin_row_scan``) and the plan's record and
+cost starts (``k_bin_plan``) and checks them against plain prefix sums.  The GPU tests check the
+kernels themselves (parity with the oracle, and bit-identical steps for different reduction grids).
 """
 import numpy as np
 import pytest
@@ -162,3 +163,61 @@ def test_partition_empty_and_single():
     _check([5], 1, 0)
     _check([5], 8, 32768)
     _check([0, 7, 0, 0, 3], 16, 1)
+
+
+def _wave_scan_exclusive(vals, n_threads):
+    """Exclusive prefix of per-thread values as the bin kernels form it: an inclusive scan inside
+    each 64-lane wave (shifted partial sums, lanes below the shift keep theirs), the waves' totals
+    through LDS, each thread adding the totals of the waves before its own."""
+    vals = np.asarray(vals, np.int64)
+    inc = vals.copy()
+    lane = np.arange(n_threads) % 64
+    o = 1
+    while o < 64:
+        shifted = np.zeros_like(inc)
+        shifted[o:] = inc[:-o]
+        inc = inc + np.where(lane >= o, shifted, 0)
+        o <<= 1
+    wave_tot = inc[63::64]
+    before = np.concatenate([[0], np.cumsum(wave_tot)[:-1]])[np.arange(n_threads) // 64]
+    return before + inc - vals, int(wave_tot.sum())
+
+
+@pytest.mark.parametrize("grid", [1, 7, 255, 256, 512, 1000, 2048])
+def test_row_scan_offsets(grid):
+    """bin_row_scan: 256 threads, each summing `per` consecutive blocks' counts, then the wave scan;
+    the offsets of every (bin, block) must be the plain exclusive prefix of the counts."""
+    rng = np.random.default_rng(grid)
+    counts = rng.integers(0, 600, grid)
+    counts[rng.random(grid) < 0.2] = 0
+    per = _ceil_div(grid, 256)
+    s = np.array([counts[t * per:min(grid, t * per + per)].sum() for t in range(256)])
+    ex, total = _wave_scan_exclusive(s, 256)
+    rel = np.zeros(grid, np.int64)
+    for t in range(256):
+        run = ex[t]
+        for w in range(t * per, min(grid, t * per + per)):
+            rel[w] = run
+            run += counts[w]
+    assert total == counts.sum()
+    assert np.array_equal(rel, np.concatenate([[0], np.cumsum(counts)[:-1]]))
+
+
+@pytest.mark.parametrize("n_bins", [1, 29, 745, 1024, 3000])
+def test_plan_scan_starts(n_bins):
+    """k_bin_plan: 1024 threads, each summing its bins' records and costs (records + F per
+    non-empty bin), then the wave scans; every thread's record and cost start must be the exclusive
+    prefix over the bins before its own, and the totals the sums."""
+    rng = np.random.default_rng(n_bins)
+    F = 32768
+    tot = rng.integers(0, 60000, n_bins)
+    tot[rng.random(n_bins) < 0.1] = 0
+    per = _ceil_div(n_bins, 1024)
+    rec = np.array([tot[t * per:min(n_bins, t * per + per)].sum() for t in range(1024)])
+    cost = np.array([(tot[t * per:min(n_bins, t * per + per)] + F * (tot[t * per:min(n_bins, t * per + per)] > 0)).sum()
+                     for t in range(1024)])
+    rex, T = _wave_scan_exclusive(rec, 1024)
+    cex, C = _wave_scan_exclusive(cost, 1024)
+    assert T == tot.sum() and C == (tot + F * (tot > 0)).sum()
+    assert np.array_equal(rex, np.concatenate([[0], np.cumsum(rec)[:-1]]))
+    assert np.array_equal(cex, np.concatenate([[0], np.cumsum(cost)[:-1]]))
